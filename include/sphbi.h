@@ -1,0 +1,153 @@
+/*
+ * sphbi.h -- analytic SPH boundary integrals on AMD Instinct MI355X (gfx950).
+ *
+ * For every (particle, boundary triangle) pair inside the kernel support the
+ * library evaluates, in closed form,
+ *
+ *     I(x) = int_T A_T(x') W(|x - x'|) dx'          (Sec. 2, eq. sphintegral,
+ *     G(x) = int_T A_T(x') grad_x W(|x - x'|) dx'    eq. nablaIntegral, eq. boundaryint)
+ *
+ * for a compact polynomial kernel W(r) = c_d h^-2 k(r/h) (Sec. 2) and a
+ * polynomial field A_T on the triangle (Sec. 3): constant (1 value per
+ * triangle), linear (3 vertex values, barycentric interpolation) or cubic
+ * Lagrange (10 values).  Per particle the results are summed over its
+ * triangles (eq. boundaryint).  Each pair is decomposed into
+ * particle-anchored pieces (Sec. 4) evaluated with Chebyshev angular terms and
+ * the hypergeometric radial term (Sec. 5).
+ *
+ * Conventions
+ *  - h is the support radius: W vanishes for |x - x'| >= h.
+ *  - All array arguments are DEVICE pointers owned by the caller unless the
+ *    argument says "host".  Nothing is freed by the library.  Calls are
+ *    asynchronous on `stream` (a hipStream_t; NULL = default stream) unless
+ *    documented as synchronising.
+ *  - Arrays are structure-of-arrays, float64, 8-byte aligned:
+ *      px, py            [N]
+ *      tri               [6][T]  rows x0, y0, x1, y1, x2, y2
+ *      nodal             [n_nodes][T]
+ *      offsets           int64 [N+1] CSR row pointer (pairs of particle i are
+ *                        offsets[i] .. offsets[i+1]-1)
+ *      tri_idx           int32 [P]   triangle of each pair
+ *      I, Gx, Gy         [N]
+ *      per_pair          [3][P] rows I, Gx, Gy (optional, may be NULL)
+ *  - Cubic node order: v0, v1, v2; edge v0->v1 at 1/3 and 2/3; edge v1->v2 at
+ *    1/3, 2/3; edge v2->v0 at 1/3, 2/3; centroid.
+ *  - Zero-area triangles contribute 0.  Either vertex orientation gives the
+ *    same result.  Overlapping triangles are summed, not checked (Sec. 2).
+ *  - Return value: SPHBI_OK or a negative status; sphbi_last_error() gives a
+ *    message (thread-local).
+ */
+#ifndef SPHBI_H
+#define SPHBI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPHBI_OK 0
+#define SPHBI_EINVAL -1       /* bad argument (null pointer, h <= 0, sizes, degree, n_nodes) */
+#define SPHBI_EUNSUPPORTED -2 /* valid but not implemented combination */
+#define SPHBI_EDEVICE -3      /* HIP launch or runtime error */
+#define SPHBI_ENOWORKSPACE -4 /* workspace missing or too small */
+#define SPHBI_ECAPACITY -5    /* output capacity too small (count returned) */
+
+#define SPHBI_WENDLAND_C2 0
+#define SPHBI_WENDLAND_C4 1
+#define SPHBI_WENDLAND_C6 2
+#define SPHBI_CUBIC_BSPLINE 3
+
+#define SPHBI_FP64 0
+#define SPHBI_MIXED 1
+
+/* Kernel k(q) = sum_p [q < radius[p]] sum_k b[p][k] q^k (q = r/h), with
+ * W(r) = c_d h^-2 k(r/h) (Sec. 2: compact polynomial kernels; piecewise
+ * kernels such as B-splines are handled piece by piece).  n_pieces 1 or 2,
+ * degree[p] <= 11, 0 < radius[p] <= 1. */
+typedef struct {
+    int32_t n_pieces;
+    int32_t degree[2];
+    int32_t reserved;
+    double radius[2];
+    double b[2][12];
+    double c_d;
+} sphbi_kernel;
+
+typedef struct {
+    int32_t precision; /* SPHBI_FP64 or SPHBI_MIXED */
+    int32_t reserved;
+    double tau_edge;   /* MIXED: pairs whose particle lies within tau_edge*h of an
+                          edge line or vertex are evaluated in FP64 (default 1e-4) */
+} sphbi_opts;
+
+/* Fills *out with a preset kernel: Wendland C2 (1-q)^4(1+4q), C4
+ * (1-q)^6(1+6q+35/3 q^2), C6 (1-q)^8(1+8q+25q^2+32q^3), cubic B-spline
+ * (1-q)^3 - 4(1/2-q)^3_+; c_d normalises the kernel to unit integral over the
+ * support disc.  Host only. */
+int sphbi_kernel_preset(int32_t id, sphbi_kernel *out);
+
+/* Default options (FP64, tau_edge = 1e-4).  Host only. */
+void sphbi_default_opts(sphbi_opts *out);
+
+/* Message of the last failing call on this thread. */
+const char *sphbi_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Pair enumeration (the neighbour set N_T of Sec. 2, eq. boundaryint):
+ * pairs (i, j) with dist(x_i, T_j) < h, grouped by particle, triangles in
+ * ascending index order within a particle.
+ *
+ * sphbi_pairlist_plan: sizes the uniform cell grid (cell >= h) over the
+ * particles' bounding box and returns the workspace the two later calls need.
+ * Synchronises `stream`.
+ *
+ * sphbi_pairlist_count: builds the grid in `ws`, counts the pairs of every
+ * particle and writes offsets[0..N]; *n_pairs (host) receives offsets[N].
+ * Synchronises `stream`.
+ *
+ * sphbi_pairlist_fill: writes tri_idx[0 .. n_pairs-1] using the offsets and
+ * the grid left in `ws` by the count call.  Asynchronous.  cap is the length
+ * of tri_idx; cap < n_pairs returns SPHBI_ECAPACITY.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    double x0, y0, cell;
+    int32_t nx, ny;
+    int64_t n_refs; /* triangle-to-cell registrations */
+} sphbi_grid;
+
+int sphbi_pairlist_plan(int64_t N, const double *px, const double *py, int64_t T, const double *tri,
+                        double h, sphbi_grid *grid /* host out */, size_t *ws_bytes /* host out */,
+                        void *stream);
+int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t T, const double *tri,
+                         double h, const sphbi_grid *grid /* host */, void *ws, size_t ws_bytes,
+                         int64_t *offsets, int64_t *n_pairs /* host out */, void *stream);
+int sphbi_pairlist_fill(int64_t N, const double *px, const double *py, int64_t T, const double *tri,
+                        double h, const sphbi_grid *grid /* host */, void *ws, size_t ws_bytes,
+                        const int64_t *offsets, int32_t *tri_idx, int64_t cap, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Forward integrals (eq. boundaryint and its gradient; Sec. 3-5).
+ *
+ * sphbi_integrate_workspace: bytes of device workspace sphbi_integrate needs
+ * for T triangles (per-triangle field records, 128 B each).  Host only.
+ *
+ * sphbi_integrate: I, Gx, Gy [N] per particle = sum over its pairs; if
+ * per_pair is not NULL also the per-pair values [3][P].  Positions and h in
+ * world units; the gradient carries the 1/h of the normalisation (Sec. 2).
+ * ws/ws_bytes: device workspace of at least sphbi_integrate_workspace(T)
+ * bytes; the call overwrites it.  Asynchronous.
+ * ------------------------------------------------------------------- */
+size_t sphbi_integrate_workspace(int64_t T);
+
+int sphbi_integrate(const sphbi_kernel *kernel /* host */, const sphbi_opts *opts /* host, NULL = default */,
+                    double h, int32_t n_nodes, int64_t N, const double *px, const double *py, int64_t T,
+                    const double *tri, const double *nodal, const int64_t *offsets, const int32_t *tri_idx,
+                    int64_t n_pairs, double *I, double *Gx, double *Gy, double *per_pair, void *ws,
+                    size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPHBI_H */

@@ -1,0 +1,168 @@
+"""Analytic SPH boundary integrals on MI355X -- Python binding.
+
+Thin ctypes wrapper over the C-ABI of ``libsphbi.so`` (see ``include/sphbi.h``).
+It only marshals torch tensors (device memory) and the current HIP stream to
+the library; every step of the computation runs in the library's kernels.
+There is no fallback: if the library is missing the call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+from . import workloads  # noqa: F401  (seeded input generators)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsphbi.so")
+
+WENDLAND_C2, WENDLAND_C4, WENDLAND_C6, CUBIC_BSPLINE = 0, 1, 2, 3
+FP64, MIXED = 0, 1
+STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENOWORKSPACE", -5: "ECAPACITY"}
+
+EXPORTS = ["sphbi_kernel_preset", "sphbi_default_opts", "sphbi_last_error", "sphbi_pairlist_plan",
+           "sphbi_pairlist_count", "sphbi_pairlist_fill", "sphbi_integrate_workspace", "sphbi_integrate"]
+
+
+class SphbiKernel(C.Structure):
+    _fields_ = [("n_pieces", C.c_int32), ("degree", C.c_int32 * 2), ("reserved", C.c_int32),
+                ("radius", C.c_double * 2), ("b", (C.c_double * 12) * 2), ("c_d", C.c_double)]
+
+
+class SphbiOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("reserved", C.c_int32), ("tau_edge", C.c_double)]
+
+
+class SphbiGrid(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("cell", C.c_double), ("nx", C.c_int32),
+                ("ny", C.c_int32), ("n_refs", C.c_int64)]
+
+
+class SphbiError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libsphbi.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SphbiError(f"{LIB_PATH} missing: build it with paper_2507_21686_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        L.sphbi_kernel_preset.argtypes = [i32, C.POINTER(SphbiKernel)]
+        L.sphbi_default_opts.argtypes = [C.POINTER(SphbiOpts)]
+        L.sphbi_default_opts.restype = None
+        L.sphbi_last_error.restype = C.c_char_p
+        L.sphbi_pairlist_plan.argtypes = [i64, vp, vp, i64, vp, d, C.POINTER(SphbiGrid), C.POINTER(C.c_size_t), vp]
+        L.sphbi_pairlist_count.argtypes = [i64, vp, vp, i64, vp, d, C.POINTER(SphbiGrid), vp, C.c_size_t, vp,
+                                           C.POINTER(C.c_int64), vp]
+        L.sphbi_pairlist_fill.argtypes = [i64, vp, vp, i64, vp, d, C.POINTER(SphbiGrid), vp, C.c_size_t, vp, vp,
+                                          i64, vp]
+        L.sphbi_integrate_workspace.argtypes = [i64]
+        L.sphbi_integrate_workspace.restype = C.c_size_t
+        L.sphbi_integrate.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, i32, i64, vp, vp, i64, vp,
+                                      vp, vp, vp, i64, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = lib().sphbi_last_error().decode()
+        raise SphbiError(f"{what} failed: {STATUS.get(rc, rc)}: {msg}")
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(None)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype=torch.float64):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise SphbiError(f"expected a contiguous {dtype} tensor on the GPU")
+    return t
+
+
+def kernel_preset(kernel_id: int) -> SphbiKernel:
+    k = SphbiKernel()
+    _check(lib().sphbi_kernel_preset(int(kernel_id), C.byref(k)), "sphbi_kernel_preset")
+    return k
+
+
+def opts(precision: int = FP64, tau_edge: float = 1e-4) -> SphbiOpts:
+    o = SphbiOpts()
+    lib().sphbi_default_opts(C.byref(o))
+    o.precision = precision
+    o.tau_edge = tau_edge
+    return o
+
+
+def pairlist(px, py, tri, h: float):
+    """Pairs with dist(x_i, T_j) < h as CSR: (offsets int64 [N+1], tri_idx int32 [P])."""
+    px, py, tri = _dev(px), _dev(py), _dev(tri)
+    N, T = px.numel(), tri.shape[1]
+    L, s = lib(), _stream()
+    grid = SphbiGrid()
+    ws_bytes = C.c_size_t(0)
+    _check(L.sphbi_pairlist_plan(N, _ptr(px), _ptr(py), T, _ptr(tri), float(h), C.byref(grid), C.byref(ws_bytes), s),
+           "sphbi_pairlist_plan")
+    ws = torch.empty(max(int(ws_bytes.value), 1), dtype=torch.uint8, device=px.device)
+    offsets = torch.empty(N + 1, dtype=torch.int64, device=px.device)
+    n = C.c_int64(0)
+    _check(L.sphbi_pairlist_count(N, _ptr(px), _ptr(py), T, _ptr(tri), float(h), C.byref(grid), _ptr(ws),
+                                  ws.numel(), _ptr(offsets), C.byref(n), s), "sphbi_pairlist_count")
+    tri_idx = torch.empty(max(int(n.value), 1), dtype=torch.int32, device=px.device)
+    _check(L.sphbi_pairlist_fill(N, _ptr(px), _ptr(py), T, _ptr(tri), float(h), C.byref(grid), _ptr(ws), ws.numel(),
+                                 _ptr(offsets), _ptr(tri_idx), int(n.value), s), "sphbi_pairlist_fill")
+    return offsets, tri_idx[: int(n.value)]
+
+
+class Integrator:
+    """Holds the kernel description and a reusable workspace for repeated calls."""
+
+    def __init__(self, kernel, h: float, n_nodes: int, precision: int = FP64, tau_edge: float = 1e-4):
+        self.kernel = kernel_preset(kernel) if isinstance(kernel, int) else kernel
+        self.h = float(h)
+        self.n_nodes = int(n_nodes)
+        self.opts = opts(precision, tau_edge)
+        self.ws = None
+
+    def workspace(self, T, device):
+        need = int(lib().sphbi_integrate_workspace(T))
+        if self.ws is None or self.ws.numel() < need or self.ws.device != device:
+            self.ws = torch.empty(need, dtype=torch.uint8, device=device)
+        return self.ws
+
+    def __call__(self, px, py, tri, nodal, offsets, tri_idx, per_pair: bool = False, out=None):
+        px, py, tri, nodal = _dev(px), _dev(py), _dev(tri), _dev(nodal)
+        offsets, tri_idx = _dev(offsets, torch.int64), _dev(tri_idx, torch.int32)
+        N, T, P = px.numel(), tri.shape[1], tri_idx.numel()
+        if nodal.shape[0] != self.n_nodes or nodal.shape[1] != T:
+            raise SphbiError("nodal must be [n_nodes, T]")
+        if out is None:
+            I = torch.empty(N, dtype=torch.float64, device=px.device)
+            Gx = torch.empty_like(I)
+            Gy = torch.empty_like(I)
+        else:
+            I, Gx, Gy = out
+        pp = torch.empty((3, P), dtype=torch.float64, device=px.device) if per_pair else None
+        ws = self.workspace(T, px.device)
+        _check(lib().sphbi_integrate(C.byref(self.kernel), C.byref(self.opts), self.h, self.n_nodes, N, _ptr(px),
+                                     _ptr(py), T, _ptr(tri), _ptr(nodal), _ptr(offsets), _ptr(tri_idx), P, _ptr(I),
+                                     _ptr(Gx), _ptr(Gy), _ptr(pp), _ptr(ws), ws.numel(), _stream()),
+               "sphbi_integrate")
+        return (I, Gx, Gy, pp) if per_pair else (I, Gx, Gy)
+
+
+def integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx, per_pair=False, precision=FP64, tau_edge=1e-4):
+    """Per-particle (I, Gx, Gy) [N] (and optionally per-pair [3, P]) on the GPU."""
+    return Integrator(kernel, h, nodal.shape[0], precision, tau_edge)(px, py, tri, nodal, offsets, tri_idx,
+                                                                      per_pair=per_pair)

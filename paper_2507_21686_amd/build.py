@@ -1,0 +1,41 @@
+"""Builds the device library ``libsphbi.so`` for gfx950 with hipcc.
+
+The library is built in-tree (next to this file) so that it travels with the
+source tree.  Every HIP translation unit is compiled with packed FP32
+instructions disabled.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libsphbi.so")
+SOURCES = ["capi.hip", "forward.hip"]
+ARCH = os.environ.get("SPHBI_OFFLOAD_ARCH", "gfx950")
+
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-command-line-argument"]
+
+
+def sources():
+    return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the HIP sources into ``libsphbi.so`` (always recompiles)."""
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc"] + FLAGS + ["-o", tmp] + sources()
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + res.stderr[-4000:])
+    if verbose and res.stderr:
+        print(res.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,499 @@
+// C-ABI entry points: kernel presets, argument validation, workspace sizing,
+// pair enumeration (uniform cell grid) and dispatch of the forward kernels.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <hipcub/hipcub.hpp>
+
+#include "internal.h"
+
+namespace sphbi {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+static bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+#define CHECK_HIP(expr)                                                              \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            set_error("%s: %s", #expr, hipGetErrorString(e_));                       \
+            return SPHBI_EDEVICE;                                                    \
+        }                                                                            \
+    } while (0)
+
+// ----------------------------------------------------------------------------
+// kernel presets: expand (1 - q/R)^a g(q/R) into monomials of q
+// ----------------------------------------------------------------------------
+static int expand_piece(int a, const double *g, int ng, double R, double *b) {
+    double c[16] = {0};
+    c[0] = 1.0;
+    int n = 1;
+    for (int i = 0; i < a; ++i) {
+        for (int j = n; j >= 1; --j) c[j] -= c[j - 1];
+        ++n;
+    }
+    double r[16] = {0};
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < ng; ++j) r[i + j] += c[i] * g[j];
+    const int deg = n + ng - 2;
+    double Rk = 1.0;
+    for (int k = 0; k <= deg; ++k) {
+        b[k] = r[k] / Rk;
+        Rk *= R;
+    }
+    return deg;
+}
+
+static double piece_mass(const double *b, int deg, double R) {   // int_0^R k(q) q dq
+    double s = 0.0;
+    for (int k = 0; k <= deg; ++k) s += b[k] * pow(R, k + 2) / (k + 2);
+    return s;
+}
+
+}  // namespace sphbi
+
+using namespace sphbi;
+
+extern "C" {
+
+const char *sphbi_last_error(void) { return g_err; }
+
+void sphbi_default_opts(sphbi_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->precision = SPHBI_FP64;
+    o->tau_edge = 1e-4;
+}
+
+int sphbi_kernel_preset(int32_t id, sphbi_kernel *out) {
+    if (!out) { set_error("sphbi_kernel_preset: out is NULL"); return SPHBI_EINVAL; }
+    memset(out, 0, sizeof(*out));
+    static const double gC2[2] = {1.0, 4.0};
+    static const double gC4[3] = {1.0, 6.0, 35.0 / 3.0};
+    static const double gC6[4] = {1.0, 8.0, 25.0, 32.0};
+    static const double one[1] = {1.0}, half[1] = {-0.5};
+    switch (id) {
+    case SPHBI_WENDLAND_C2: out->n_pieces = 1; out->radius[0] = 1.0; out->degree[0] = expand_piece(4, gC2, 2, 1.0, out->b[0]); break;
+    case SPHBI_WENDLAND_C4: out->n_pieces = 1; out->radius[0] = 1.0; out->degree[0] = expand_piece(6, gC4, 3, 1.0, out->b[0]); break;
+    case SPHBI_WENDLAND_C6: out->n_pieces = 1; out->radius[0] = 1.0; out->degree[0] = expand_piece(8, gC6, 4, 1.0, out->b[0]); break;
+    case SPHBI_CUBIC_BSPLINE:
+        out->n_pieces = 2;
+        out->radius[0] = 1.0;
+        out->degree[0] = expand_piece(3, one, 1, 1.0, out->b[0]);
+        out->radius[1] = 0.5;
+        out->degree[1] = expand_piece(3, half, 1, 0.5, out->b[1]);   // -4 (1/2 - q)^3 = -1/2 (1 - 2q)^3
+        break;
+    default: set_error("unknown kernel preset %d", id); return SPHBI_EINVAL;
+    }
+    double mass = 0.0;
+    for (int p = 0; p < out->n_pieces; ++p) mass += piece_mass(out->b[p], out->degree[p], out->radius[p]);
+    out->c_d = 1.0 / (2.0 * M_PI * mass);
+    return SPHBI_OK;
+}
+
+}  // extern "C"
+
+namespace sphbi {
+
+static int validate_kernel(const sphbi_kernel *k) {
+    if (!k) { set_error("kernel is NULL"); return SPHBI_EINVAL; }
+    if (k->n_pieces < 1 || k->n_pieces > 2) { set_error("n_pieces must be 1 or 2"); return SPHBI_EINVAL; }
+    for (int p = 0; p < k->n_pieces; ++p) {
+        if (k->degree[p] < 0 || k->degree[p] > kMaxDeg) { set_error("degree must be in [0, 11]"); return SPHBI_EINVAL; }
+        if (!(k->radius[p] > 0.0 && k->radius[p] <= 1.0)) { set_error("radius must be in (0, 1]"); return SPHBI_EINVAL; }
+    }
+    if (!isfinite(k->c_d)) { set_error("c_d not finite"); return SPHBI_EINVAL; }
+    return SPHBI_OK;
+}
+
+KArgs make_kargs(const sphbi_kernel *k, int *deg_out) {
+    KArgs K;
+    memset(&K, 0, sizeof(K));
+    K.npieces = k->n_pieces;
+    K.cd = k->c_d;
+    int deg = 0;
+    for (int p = 0; p < k->n_pieces; ++p) {
+        const double R = k->radius[p];
+        K.R[p] = R;
+        if (k->degree[p] > deg) deg = k->degree[p];
+        for (int m = 0; m <= kMaxOrder; ++m) {
+            double sv = 0.0, sw = 0.0;
+            for (int j = 0; j <= k->degree[p]; ++j) {
+                const double b = k->b[p][j];
+                K.bq[p][m][j] = b / (j + 2 + m);
+                K.kbq[p][m][j] = j * b / (j + 1 + m);
+                sv += b * pow(R, j + 2 + m) / (j + 2 + m);
+                sw += j * b * pow(R, j + 1 + m) / (j + 1 + m);
+            }
+            K.sv[p][m] = sv;
+            K.sw[p][m] = sw;
+        }
+    }
+    *deg_out = deg;
+    return K;
+}
+
+// ----------------------------------------------------------------------------
+// pair enumeration kernels
+// ----------------------------------------------------------------------------
+struct GridDev {
+    double x0, y0, icell;
+    int nx, ny;
+};
+
+__global__ void bbox_partial(int64_t N, const double *__restrict__ px, const double *__restrict__ py,
+                             double *__restrict__ part) {
+    __shared__ double s[4][256];
+    double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+        const double x = px[i], y = py[i];
+        mnx = fmin(mnx, x); mxx = fmax(mxx, x);
+        mny = fmin(mny, y); mxy = fmax(mxy, y);
+    }
+    s[0][threadIdx.x] = mnx; s[1][threadIdx.x] = mny; s[2][threadIdx.x] = mxx; s[3][threadIdx.x] = mxy;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            s[1][threadIdx.x] = fmin(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+            s[2][threadIdx.x] = fmax(s[2][threadIdx.x], s[2][threadIdx.x + w]);
+            s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__device__ inline void tri_cells(const GridDev &g, const double *__restrict__ tri, int64_t T, int64_t t, double h,
+                                 int &cx0, int &cx1, int &cy0, int &cy1) {
+    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const double x = tri[(2 * v) * T + t], y = tri[(2 * v + 1) * T + t];
+        xmin = fmin(xmin, x); xmax = fmax(xmax, x);
+        ymin = fmin(ymin, y); ymax = fmax(ymax, y);
+    }
+    const double fx0 = floor((xmin - h - g.x0) * g.icell), fx1 = floor((xmax + h - g.x0) * g.icell);
+    const double fy0 = floor((ymin - h - g.y0) * g.icell), fy1 = floor((ymax + h - g.y0) * g.icell);
+    // clamp to the grid; an empty range when the box misses it (also for non-finite input)
+    cx0 = (int)fmax(fx0, 0.0);
+    cy0 = (int)fmax(fy0, 0.0);
+    cx1 = (int)fmin(fx1, (double)(g.nx - 1));
+    cy1 = (int)fmin(fy1, (double)(g.ny - 1));
+    if (!(fx1 >= 0.0) || !(fy1 >= 0.0) || !(fx0 <= g.nx - 1) || !(fy0 <= g.ny - 1)) { cx1 = cx0 - 1; cy1 = cy0 - 1; }
+}
+
+__global__ void tri_ref_count(GridDev g, int64_t T, const double *__restrict__ tri, double h,
+                              unsigned long long *__restrict__ total, int *__restrict__ cell_count) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    int cx0, cx1, cy0, cy1;
+    tri_cells(g, tri, T, t, h, cx0, cx1, cy0, cy1);
+    if (cx1 < cx0 || cy1 < cy0) return;
+    if (total) atomicAdd(total, (unsigned long long)(cx1 - cx0 + 1) * (unsigned long long)(cy1 - cy0 + 1));
+    if (cell_count)
+        for (int cy = cy0; cy <= cy1; ++cy)
+            for (int cx = cx0; cx <= cx1; ++cx) atomicAdd(&cell_count[cy * g.nx + cx], 1);
+}
+
+__global__ void tri_ref_fill(GridDev g, int64_t T, const double *__restrict__ tri, double h,
+                             const int *__restrict__ cell_start, int *__restrict__ cursor,
+                             int *__restrict__ items, int64_t n_refs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    int cx0, cx1, cy0, cy1;
+    tri_cells(g, tri, T, t, h, cx0, cx1, cy0, cy1);
+    for (int cy = cy0; cy <= cy1; ++cy)
+        for (int cx = cx0; cx <= cx1; ++cx) {
+            const int c = cy * g.nx + cx;
+            const int slot = cell_start[c] + atomicAdd(&cursor[c], 1);
+            if (slot < n_refs) items[slot] = (int)t;
+        }
+}
+
+// squared distance from (x, y) to triangle t (0 inside)
+__device__ inline double dist2_tri(double x, double y, const double *__restrict__ tri, int64_t T, int64_t t) {
+    const double x0 = tri[t], y0 = tri[T + t], x1 = tri[2 * T + t], y1 = tri[3 * T + t];
+    const double x2 = tri[4 * T + t], y2 = tri[5 * T + t];
+    const double c0 = (x1 - x0) * (y - y0) - (y1 - y0) * (x - x0);
+    const double c1 = (x2 - x1) * (y - y1) - (y2 - y1) * (x - x1);
+    const double c2 = (x0 - x2) * (y - y2) - (y0 - y2) * (x - x2);
+    if ((c0 >= 0.0 && c1 >= 0.0 && c2 >= 0.0) || (c0 <= 0.0 && c1 <= 0.0 && c2 <= 0.0)) return 0.0;
+    double best = INFINITY;
+    const double ex[3] = {x0, x1, x2}, ey[3] = {y0, y1, y2};
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const double ax = ex[e], ay = ey[e], bx = ex[(e + 1) % 3], by = ey[(e + 1) % 3];
+        const double dx = bx - ax, dy = by - ay;
+        const double L = dx * dx + dy * dy;
+        double s = L > 0.0 ? ((x - ax) * dx + (y - ay) * dy) / L : 0.0;
+        s = fmin(fmax(s, 0.0), 1.0);
+        const double qx = ax + s * dx - x, qy = ay + s * dy - y;
+        best = fmin(best, qx * qx + qy * qy);
+    }
+    return best;
+}
+
+__device__ inline int particle_cell(const GridDev &g, double x, double y) {
+    int cx = (int)fmin(fmax(floor((x - g.x0) * g.icell), 0.0), (double)(g.nx - 1));
+    int cy = (int)fmin(fmax(floor((y - g.y0) * g.icell), 0.0), (double)(g.ny - 1));
+    return cy * g.nx + cx;
+}
+
+__global__ void pair_count(GridDev g, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
+                           int64_t T, const double *__restrict__ tri, double h2, const int *__restrict__ cell_start,
+                           const int *__restrict__ items, int64_t *__restrict__ counts) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double x = px[i], y = py[i];
+    const int c = particle_cell(g, x, y);
+    int64_t n = 0;
+    for (int k = cell_start[c]; k < cell_start[c + 1]; ++k)
+        if (dist2_tri(x, y, tri, T, items[k]) < h2) ++n;
+    counts[i] = n;
+}
+
+__global__ void pair_fill(GridDev g, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
+                          int64_t T, const double *__restrict__ tri, double h2, const int *__restrict__ cell_start,
+                          const int *__restrict__ items, const int64_t *__restrict__ offsets,
+                          int32_t *__restrict__ tri_idx, int64_t cap) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double x = px[i], y = py[i];
+    const int c = particle_cell(g, x, y);
+    const int64_t q0 = offsets[i], q1 = offsets[i + 1] < cap ? offsets[i + 1] : cap;
+    int64_t q = q0;
+    for (int k = cell_start[c]; k < cell_start[c + 1] && q < q1; ++k) {
+        const int t = items[k];
+        if (dist2_tri(x, y, tri, T, t) < h2) tri_idx[q++] = t;
+    }
+    // ascending triangle order (cell lists are filled with atomics)
+    for (int64_t a = q0 + 1; a < q; ++a) {
+        const int32_t v = tri_idx[a];
+        int64_t b = a - 1;
+        while (b >= q0 && tri_idx[b] > v) { tri_idx[b + 1] = tri_idx[b]; --b; }
+        tri_idx[b + 1] = v;
+    }
+}
+
+__global__ void write_zero_i64(int64_t *p) { *p = 0; }
+
+struct WsLayout {
+    size_t cell_start, cursor, items, scan_tmp, scan_tmp_bytes, total;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int layout(const sphbi_grid *g, int64_t N, WsLayout *L) {
+    const size_t ncell = (size_t)g->nx * g->ny;
+    size_t t1 = 0, t2 = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, t1, (int *)nullptr, (int *)nullptr, (int)(ncell + 1));
+    (void)hipcub::DeviceScan::InclusiveSum(nullptr, t2, (int64_t *)nullptr, (int64_t *)nullptr, (int)(N > 0 ? N : 1));
+    size_t o = 0;
+    L->cell_start = o; o = align256(o + (ncell + 1) * sizeof(int));
+    L->cursor = o; o = align256(o + (ncell + 1) * sizeof(int));
+    L->items = o; o = align256(o + (size_t)(g->n_refs > 0 ? g->n_refs : 1) * sizeof(int));
+    L->scan_tmp = o;
+    L->scan_tmp_bytes = t1 > t2 ? t1 : t2;
+    o = align256(o + L->scan_tmp_bytes);
+    L->total = o;
+    return SPHBI_OK;
+}
+
+static int check_pairlist_args(int64_t N, const double *px, const double *py, int64_t T, const double *tri,
+                               double h) {
+    if (N < 0 || T < 0) { set_error("negative size"); return SPHBI_EINVAL; }
+    if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
+    if (N > 0 && (!px || !py)) { set_error("particle arrays are NULL"); return SPHBI_EINVAL; }
+    if (T > 0 && !tri) { set_error("triangle array is NULL"); return SPHBI_EINVAL; }
+    if (!aligned8(px) || !aligned8(py) || !aligned8(tri)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
+    if (T > INT32_MAX) { set_error("more than 2^31-1 triangles"); return SPHBI_EUNSUPPORTED; }
+    return SPHBI_OK;
+}
+
+static GridDev to_dev(const sphbi_grid *g) {
+    GridDev d;
+    d.x0 = g->x0; d.y0 = g->y0; d.icell = 1.0 / g->cell; d.nx = g->nx; d.ny = g->ny;
+    return d;
+}
+
+}  // namespace sphbi
+
+extern "C" {
+
+int sphbi_pairlist_plan(int64_t N, const double *px, const double *py, int64_t T, const double *tri, double h,
+                        sphbi_grid *grid, size_t *ws_bytes, void *stream) {
+    int rc = check_pairlist_args(N, px, py, T, tri, h);
+    if (rc) return rc;
+    if (!grid || !ws_bytes) { set_error("grid/ws_bytes outputs are NULL"); return SPHBI_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    memset(grid, 0, sizeof(*grid));
+    double bb[4] = {0.0, 0.0, 0.0, 0.0};
+    void *tmp = nullptr;
+    if (N > 0) {
+        const int nb = (int)((N + 255) / 256 < 1024 ? (N + 255) / 256 : 1024);
+        CHECK_HIP(hipMallocAsync(&tmp, sizeof(double) * 4 * nb + sizeof(unsigned long long), s));
+        hipLaunchKernelGGL(bbox_partial, dim3(nb), dim3(256), 0, s, N, px, py, (double *)tmp);
+        CHECK_HIP(hipGetLastError());
+        double *hp = (double *)malloc(sizeof(double) * 4 * nb);
+        CHECK_HIP(hipMemcpyAsync(hp, tmp, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        bb[0] = INFINITY; bb[1] = INFINITY; bb[2] = -INFINITY; bb[3] = -INFINITY;
+        for (int b = 0; b < nb; ++b) {
+            bb[0] = fmin(bb[0], hp[4 * b]); bb[1] = fmin(bb[1], hp[4 * b + 1]);
+            bb[2] = fmax(bb[2], hp[4 * b + 2]); bb[3] = fmax(bb[3], hp[4 * b + 3]);
+        }
+        free(hp);
+        if (!isfinite(bb[0]) || !isfinite(bb[1]) || !isfinite(bb[2]) || !isfinite(bb[3])) {
+            (void)hipFreeAsync(tmp, s);
+            set_error("non-finite particle coordinates");
+            return SPHBI_EINVAL;
+        }
+    }
+    const double ext = fmax(bb[2] - bb[0], bb[3] - bb[1]);
+    double cell = h;
+    if (ext / cell > 4096.0) cell = ext / 4096.0;
+    grid->x0 = bb[0];
+    grid->y0 = bb[1];
+    grid->cell = cell;
+    grid->nx = (int)floor((bb[2] - bb[0]) / cell) + 1;
+    grid->ny = (int)floor((bb[3] - bb[1]) / cell) + 1;
+    grid->n_refs = 0;
+    if (N > 0 && T > 0) {
+        unsigned long long *tot = (unsigned long long *)((char *)tmp + sizeof(double) * 4 *
+                                  ((N + 255) / 256 < 1024 ? (N + 255) / 256 : 1024));
+        hipLaunchKernelGGL(write_zero_i64, dim3(1), dim3(1), 0, s, (int64_t *)tot);
+        GridDev g = to_dev(grid);
+        hipLaunchKernelGGL(tri_ref_count, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, T, tri, h, tot,
+                           (int *)nullptr);
+        CHECK_HIP(hipGetLastError());
+        unsigned long long n = 0;
+        CHECK_HIP(hipMemcpyAsync(&n, tot, sizeof(n), hipMemcpyDeviceToHost, s));
+        CHECK_HIP(hipStreamSynchronize(s));
+        if (n > (unsigned long long)INT32_MAX) {
+            (void)hipFreeAsync(tmp, s);
+            set_error("grid registrations exceed 2^31");
+            return SPHBI_EUNSUPPORTED;
+        }
+        grid->n_refs = (int64_t)n;
+    }
+    if (tmp) CHECK_HIP(hipFreeAsync(tmp, s));
+    WsLayout L;
+    layout(grid, N, &L);
+    *ws_bytes = L.total;
+    return SPHBI_OK;
+}
+
+int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t T, const double *tri, double h,
+                         const sphbi_grid *grid, void *ws, size_t ws_bytes, int64_t *offsets, int64_t *n_pairs,
+                         void *stream) {
+    int rc = check_pairlist_args(N, px, py, T, tri, h);
+    if (rc) return rc;
+    if (!grid || !n_pairs || !offsets) { set_error("grid/offsets/n_pairs is NULL"); return SPHBI_EINVAL; }
+    if (grid->nx <= 0 || grid->ny <= 0 || !(grid->cell > 0)) { set_error("grid not planned"); return SPHBI_EINVAL; }
+    WsLayout L;
+    layout(grid, N, &L);
+    if (!ws || ws_bytes < L.total) { set_error("workspace too small (%zu < %zu)", ws_bytes, L.total); return SPHBI_ENOWORKSPACE; }
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    int *cell_start = (int *)(w + L.cell_start), *cursor = (int *)(w + L.cursor), *items = (int *)(w + L.items);
+    const size_t ncell = (size_t)grid->nx * grid->ny;
+    GridDev g = to_dev(grid);
+    CHECK_HIP(hipMemsetAsync(cursor, 0, (ncell + 1) * sizeof(int), s));
+    if (T > 0)
+        hipLaunchKernelGGL(tri_ref_count, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, T, tri, h,
+                           (unsigned long long *)nullptr, cursor);
+    CHECK_HIP(hipGetLastError());
+    size_t tb = L.scan_tmp_bytes;
+    CHECK_HIP(hipcub::DeviceScan::ExclusiveSum(w + L.scan_tmp, tb, cursor, cell_start, (int)(ncell + 1), s));
+    CHECK_HIP(hipMemsetAsync(cursor, 0, (ncell + 1) * sizeof(int), s));
+    if (T > 0)
+        hipLaunchKernelGGL(tri_ref_fill, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, T, tri, h,
+                           cell_start, cursor, items, grid->n_refs);
+    CHECK_HIP(hipGetLastError());
+    CHECK_HIP(hipMemsetAsync(offsets, 0, sizeof(int64_t), s));
+    if (N > 0) {
+        hipLaunchKernelGGL(pair_count, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g, N, px, py, T, tri,
+                           h * h, cell_start, items, offsets + 1);
+        CHECK_HIP(hipGetLastError());
+        tb = L.scan_tmp_bytes;
+        CHECK_HIP(hipcub::DeviceScan::InclusiveSum(w + L.scan_tmp, tb, offsets + 1, offsets + 1, (int)N, s));
+    }
+    CHECK_HIP(hipMemcpyAsync(n_pairs, offsets + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    return SPHBI_OK;
+}
+
+int sphbi_pairlist_fill(int64_t N, const double *px, const double *py, int64_t T, const double *tri, double h,
+                        const sphbi_grid *grid, void *ws, size_t ws_bytes, const int64_t *offsets, int32_t *tri_idx,
+                        int64_t cap, void *stream) {
+    int rc = check_pairlist_args(N, px, py, T, tri, h);
+    if (rc) return rc;
+    if (!grid || !offsets || (cap > 0 && !tri_idx)) { set_error("grid/offsets/tri_idx is NULL"); return SPHBI_EINVAL; }
+    WsLayout L;
+    layout(grid, N, &L);
+    if (!ws || ws_bytes < L.total) { set_error("workspace too small"); return SPHBI_ENOWORKSPACE; }
+    hipStream_t s = (hipStream_t)stream;
+    int64_t total = 0;
+    CHECK_HIP(hipMemcpyAsync(&total, offsets + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    if (total > cap) { set_error("tri_idx capacity %lld < %lld pairs", (long long)cap, (long long)total); return SPHBI_ECAPACITY; }
+    char *w = (char *)ws;
+    GridDev g = to_dev(grid);
+    if (N > 0)
+        hipLaunchKernelGGL(pair_fill, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g, N, px, py, T, tri,
+                           h * h, (const int *)(w + L.cell_start), (const int *)(w + L.items), offsets, tri_idx, cap);
+    CHECK_HIP(hipGetLastError());
+    return SPHBI_OK;
+}
+
+size_t sphbi_integrate_workspace(int64_t T) {
+    return (size_t)(T > 0 ? T : 1) * kRecDoubles * sizeof(double);
+}
+
+int sphbi_integrate(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,
+                    const double *px, const double *py, int64_t T, const double *tri, const double *nodal,
+                    const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, double *I, double *Gx,
+                    double *Gy, double *per_pair, void *ws, size_t ws_bytes, void *stream) {
+    int rc = validate_kernel(kernel);
+    if (rc) return rc;
+    sphbi_opts o;
+    sphbi_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.precision != SPHBI_FP64 && o.precision != SPHBI_MIXED) { set_error("unknown precision %d", o.precision); return SPHBI_EINVAL; }
+    if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
+    if (n_nodes != 1 && n_nodes != 3 && n_nodes != 10) { set_error("n_nodes must be 1, 3 or 10"); return SPHBI_EINVAL; }
+    if (N < 0 || T < 0 || n_pairs < 0) { set_error("negative size"); return SPHBI_EINVAL; }
+    if (T > INT32_MAX) { set_error("more than 2^31-1 triangles"); return SPHBI_EUNSUPPORTED; }
+    if (N > 0 && (!px || !py || !offsets || !I || !Gx || !Gy)) { set_error("particle arrays are NULL"); return SPHBI_EINVAL; }
+    if (n_pairs > 0 && (!tri_idx || !tri || !nodal)) { set_error("pair/triangle arrays are NULL"); return SPHBI_EINVAL; }
+    const void *ptrs[] = {px, py, tri, nodal, offsets, tri_idx, I, Gx, Gy, per_pair, ws};
+    for (const void *p : ptrs)
+        if (!aligned8(p)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
+    if (N == 0) return SPHBI_OK;
+    if (T > 0 && (!ws || ws_bytes < sphbi_integrate_workspace(T))) {
+        set_error("workspace too small (%zu < %zu)", ws_bytes, sphbi_integrate_workspace(T));
+        return SPHBI_ENOWORKSPACE;
+    }
+    int deg = 0;
+    const KArgs K = make_kargs(kernel, &deg);
+    const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
+    hipStream_t s = (hipStream_t)stream;
+    rc = launch_prepare(order, T, tri, nodal, h, (double *)ws, s);
+    if (rc) return rc;
+    return launch_forward(order, deg, o.precision, o.tau_edge, K, h, N, px, py, offsets, tri_idx, n_pairs, T,
+                          (const double *)ws, I, Gx, Gy, per_pair, s);
+}
+
+}  // extern "C"

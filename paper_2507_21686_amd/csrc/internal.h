@@ -1,0 +1,46 @@
+// Internal declarations shared by the device library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sphbi.h"
+
+namespace sphbi {
+
+constexpr int kMaxOrder = 3;    // cubic fields
+constexpr int kMaxDeg = 11;     // kernel polynomial degree
+
+// Device-side kernel description, derived on the host from sphbi_kernel.
+// bq[p][m][k]  = b_k / (k + 2 + m)     (value, field degree m)
+// kbq[p][m][k] = k b_k / (k + 1 + m)   (gradient, field degree m)
+// sv[p][m]     = sum_k b_k R^{k+2+m} / (k+2+m)   (value of a unit sector)
+// sw[p][m]     = sum_k k b_k R^{k+1+m} / (k+1+m) (gradient of a unit sector)
+struct KArgs {
+    int npieces;
+    int pad;
+    double R[2];
+    double bq[2][kMaxOrder + 1][kMaxDeg + 1];
+    double kbq[2][kMaxOrder + 1][kMaxDeg + 1];
+    double sv[2][kMaxOrder + 1];
+    double sw[2][kMaxOrder + 1];
+    double cd;
+};
+
+// Per-triangle record written by the field preparation kernel: vertices
+// (world units) and the field as a polynomial about vertex 0 in units of h,
+// A(v0 + h eta) = sum e_ij eta_x^i eta_y^j, ordered e00 e10 e01 e20 e11 e02
+// e30 e21 e12 e03.
+constexpr int kRecDoubles = 16;
+
+void set_error(const char *fmt, ...);
+KArgs make_kargs(const sphbi_kernel *k, int *deg_out);
+
+int launch_prepare(int order, int64_t T, const double *tri, const double *nodal, double h, double *rec,
+                   hipStream_t s);
+int launch_forward(int order, int deg, int precision, double tau_edge, const KArgs &K, double h, int64_t N,
+                   const double *px, const double *py, const int64_t *offsets, const int32_t *tri_idx,
+                   int64_t P, int64_t T, const double *rec, double *I, double *Gx, double *Gy, double *per_pair,
+                   hipStream_t s);
+
+}  // namespace sphbi

@@ -1,0 +1,85 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load, export every function declared in include/sphbi.h,
+reproduce the kernel presets independently of the oracle, and reject bad
+arguments before touching the device.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2507_21686_amd as sb
+from tests import exact
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "sphbi.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(sphbi_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = header_functions()
+    assert len(names) >= 8
+    L = sb.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(sb.EXPORTS) <= set(names)
+
+
+@pytest.mark.parametrize("kid", [0, 1, 2, 3])
+def test_kernel_presets(kid):
+    k = sb.kernel_preset(kid)
+    mono = exact.monomials(kid)
+    assert k.n_pieces == len(mono)
+    for p, (coef, rad) in enumerate(mono):
+        assert k.radius[p] == rad
+        assert k.degree[p] == len(coef) - 1
+        np.testing.assert_allclose([k.b[p][i] for i in range(len(coef))], coef, rtol=1e-13, atol=1e-12)
+    assert k.c_d == pytest.approx(float(exact.c_d(kid)), rel=1e-14)
+    n, R, deg, b, cd = oracle.kernel_monomials(kid)
+    assert k.c_d == pytest.approx(cd, rel=1e-14)
+
+
+def test_bad_arguments_rejected_without_device():
+    L = sb.lib()
+    k = sb.kernel_preset(0)
+    o = sb.opts()
+    z = C.c_void_p(None)
+    # h <= 0
+    rc = L.sphbi_integrate(C.byref(k), C.byref(o), 0.0, 1, 0, z, z, 0, z, z, z, z, 0, z, z, z, z, z, 0, z)
+    assert rc == -1 and b"h must be" in L.sphbi_last_error()
+    # n_nodes
+    rc = L.sphbi_integrate(C.byref(k), C.byref(o), 1.0, 4, 0, z, z, 0, z, z, z, z, 0, z, z, z, z, z, 0, z)
+    assert rc == -1
+    # NULL kernel
+    rc = L.sphbi_integrate(None, C.byref(o), 1.0, 1, 0, z, z, 0, z, z, z, z, 0, z, z, z, z, z, 0, z)
+    assert rc == -1
+    # degree out of range
+    k2 = sb.kernel_preset(0)
+    k2.degree[0] = 12
+    rc = L.sphbi_integrate(C.byref(k2), C.byref(o), 1.0, 1, 0, z, z, 0, z, z, z, z, 0, z, z, z, z, z, 0, z)
+    assert rc == -1
+    # NULL particle arrays with N > 0
+    rc = L.sphbi_integrate(C.byref(k), C.byref(o), 1.0, 1, 5, z, z, 0, z, z, z, z, 0, z, z, z, z, z, 0, z)
+    assert rc == -1
+    # unknown preset / precision
+    assert L.sphbi_kernel_preset(9, C.byref(sb.SphbiKernel())) == -1
+    o2 = sb.opts()
+    o2.precision = 7
+    rc = L.sphbi_integrate(C.byref(k), C.byref(o2), 1.0, 1, 0, z, z, 0, z, z, z, z, 0, z, z, z, z, z, 0, z)
+    assert rc == -1
+    # N = 0 is a no-op
+    rc = L.sphbi_integrate(C.byref(k), C.byref(o), 1.0, 1, 0, z, z, 0, z, z, z, z, 0, z, z, z, z, z, 0, z)
+    assert rc == 0
+
+
+def test_workspace_size():
+    assert sb.lib().sphbi_integrate_workspace(1000) == 1000 * 16 * 8
+    assert sb.lib().sphbi_integrate_workspace(0) >= 8
