@@ -198,6 +198,7 @@ typedef struct {
     double x[3], y[3];
     double D;     /* (y1-y2)(x0-x2) + (x2-x1)(y0-y2), Sec. 3 */
     double orient;
+    double elen[3], eang[3], eopp[3], ecr[3];   /* per edge: length, direction angles of e and -e, cross(e, a) */
     int nn;
     double A[10];
 } otri;
@@ -243,11 +244,21 @@ static void ray(const octx *c, double th, double out[3]) {
     double ct = cos(th), st = sin(th);
     double lo = 0.0, hi = INFINITY;
     for (int e = 0; e < 3; ++e) {
-        int a = e, b = (e + 1) % 3;
-        double ex = t->x[b] - t->x[a], ey = t->y[b] - t->y[a];
-        /* inside: cross(b-a, x-a) >= 0 ; along x = r e_theta */
-        double al = t->orient * (ex * st - ey * ct);
-        double be = t->orient * (ex * t->y[a] - ey * t->x[a]);
+        /* inside: cross(b-a, x-a) >= 0 ; along x = r e_theta this reads
+         * r |e| sin(theta - theta_e) >= cross(e, a); the sine of the angle
+         * difference keeps full relative accuracy for rays nearly parallel to
+         * the edge, where ex sin(theta) - ey cos(theta) would cancel. */
+        double d1 = th - t->eang[e], d2 = th - t->eopp[e];
+        if (d1 > OR_PI) d1 -= 2.0 * OR_PI;
+        if (d1 < -OR_PI) d1 += 2.0 * OR_PI;
+        if (d2 > OR_PI) d2 -= 2.0 * OR_PI;
+        if (d2 < -OR_PI) d2 += 2.0 * OR_PI;
+        /* sin(theta - theta_e) from whichever of the two edge directions is
+         * closer, so that both parallel and antiparallel rays keep full
+         * relative accuracy (the difference of two close angles is exact) */
+        double sn = fabs(d1) <= fabs(d2) ? sin(d1) : -sin(d2);
+        double al = t->orient * t->elen[e] * sn;
+        double be = t->orient * t->ecr[e];
         if (al > 0) { double r = be / al; if (r > lo) lo = r; }
         else if (al < 0) { double r = be / al; if (r < hi) hi = r; }
         else if (be > 0) { lo = 1.0; hi = 0.0; }
@@ -317,6 +328,14 @@ static void pair_normalised(const okern *K, otri *t, double out[3]) {
     double area2 = (t->x[1] - t->x[0]) * (t->y[2] - t->y[0]) - (t->x[2] - t->x[0]) * (t->y[1] - t->y[0]);
     if (area2 == 0.0 || !isfinite(area2)) return;           /* zero-area triangles contribute 0 */
     t->orient = area2 > 0 ? 1.0 : -1.0;                      /* inside test works for either orientation */
+    for (int e = 0; e < 3; ++e) {
+        int a = e, b = (e + 1) % 3;
+        double ex = t->x[b] - t->x[a], ey = t->y[b] - t->y[a];
+        t->elen[e] = sqrt(ex * ex + ey * ey);
+        t->eang[e] = atan2(ey, ex);
+        t->eopp[e] = atan2(-ey, -ex);
+        t->ecr[e] = ex * t->y[a] - ey * t->x[a];
+    }
     t->D = (t->y[1] - t->y[2]) * (t->x[0] - t->x[2]) + (t->x[2] - t->x[1]) * (t->y[0] - t->y[2]);
     double amax = 0.0;
     for (int i = 0; i < t->nn; ++i) amax = fmax(amax, fabs(t->A[i]));

@@ -318,3 +318,30 @@ def test_brute_force_cartesian_quadrature():
                                    epsabs=1e-12, epsrel=1e-12)[0]
         out = oracle.pair(kid, 1.0, 0, 0, np.array(tri), [1.0])
         assert abs(out[0] - I) < 1e-8
+
+
+# ---------------------------------------------------------------- mpmath brute force on hard geometry
+
+HARD = [
+    # particle 3.7e-3 from an edge line, 0.12 from a vertex
+    [[0.0740239692463632, -0.09398297285110371], [4.391007227669081, 1.5679184405214293],
+     [-0.9420411035304938, 1.1985067441341313]],
+    # particle 2.4e-4 from an edge line, ray nearly antiparallel to that edge
+    [[1.9841167067393166, -2.2439695178422516], [3.4639361499901176, 0.39653672756857644],
+     [-0.4900828293764847, -0.056374666550047435]],
+    # particle 4.7e-4 from an edge line
+    [[0.6562608579813201, -0.4267303550543204], [0.6562608579813201, 2.4195307220231443],
+     [-3.139159920024227, 2.0444958853791446]],
+]
+
+
+@pytest.mark.parametrize("case", range(len(HARD)))
+def test_definition_matches_mpmath_near_edges(case):
+    import mpmath as mp
+    from tests.mp_reference import mp_pair
+    v = HARD[case]
+    r = mp_pair(v)
+    cd = mp.mpf(7) / mp.pi
+    ref = np.array([float(cd * x) for x in r])
+    out = oracle.pair(0, 1.0, 0.0, 0.0, np.array(v).reshape(6), [1.0])
+    np.testing.assert_allclose(out, ref, rtol=0, atol=2e-15)
