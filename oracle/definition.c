@@ -239,23 +239,28 @@ typedef struct {
 } octx;
 
 /* value, and radial part of the gradient (before the -e_theta factor) */
-static void ray(const octx *c, double th, double out[3]) {
+/* Ray at angle theta = base + delta, where base is an end of the current
+ * interval and delta the (small) offset from it.  Interval ends include the
+ * edge directions exactly, so theta - theta_e = (base - theta_e) + delta
+ * keeps full relative accuracy even for rays within 1e-8 rad of an edge
+ * direction (forming theta first would lose it). */
+static double wrap_pi(double x) {
+    if (x > OR_PI) x -= 2.0 * OR_PI;
+    if (x < -OR_PI) x += 2.0 * OR_PI;
+    return x;
+}
+
+static void ray(const octx *c, double base, double delta, double out[3]) {
     const otri *t = c->t;
+    const double th = base + delta;
     double ct = cos(th), st = sin(th);
     double lo = 0.0, hi = INFINITY;
     for (int e = 0; e < 3; ++e) {
         /* inside: cross(b-a, x-a) >= 0 ; along x = r e_theta this reads
-         * r |e| sin(theta - theta_e) >= cross(e, a); the sine of the angle
-         * difference keeps full relative accuracy for rays nearly parallel to
-         * the edge, where ex sin(theta) - ey cos(theta) would cancel. */
-        double d1 = th - t->eang[e], d2 = th - t->eopp[e];
-        if (d1 > OR_PI) d1 -= 2.0 * OR_PI;
-        if (d1 < -OR_PI) d1 += 2.0 * OR_PI;
-        if (d2 > OR_PI) d2 -= 2.0 * OR_PI;
-        if (d2 < -OR_PI) d2 += 2.0 * OR_PI;
-        /* sin(theta - theta_e) from whichever of the two edge directions is
-         * closer, so that both parallel and antiparallel rays keep full
-         * relative accuracy (the difference of two close angles is exact) */
+         * r |e| sin(theta - theta_e) >= cross(e, a); the sine is taken of the
+         * angle to the nearer of the two edge directions */
+        double d1 = wrap_pi(wrap_pi(base - t->eang[e]) + delta);
+        double d2 = wrap_pi(wrap_pi(base - t->eopp[e]) + delta);
         double sn = fabs(d1) <= fabs(d2) ? sin(d1) : -sin(d2);
         double al = t->orient * t->elen[e] * sn;
         double be = t->orient * t->ecr[e];
@@ -282,12 +287,14 @@ static void ray(const octx *c, double th, double out[3]) {
 }
 
 static void glq(const octx *c, double a, double b, int n, double q[3], double *qabs) {
-    double hw = 0.5 * (b - a), md = 0.5 * (b + a);
+    double hw = 0.5 * (b - a);
     q[0] = q[1] = q[2] = 0.0;
     double s = 0.0;
     for (int i = 0; i < n; ++i) {
         double o[3];
-        ray(c, md + hw * gl_x[n][i], o);
+        double x = gl_x[n][i];
+        if (x <= 0.0) ray(c, a, hw * (1.0 + x), o);      /* offsets from the nearer end */
+        else ray(c, b, -hw * (1.0 - x), o);
         double w = hw * gl_w[n][i];
         q[0] += w * o[0]; q[1] += w * o[1]; q[2] += w * o[2];
         s += w * (fabs(o[0]) + fabs(o[1]) + fabs(o[2]));
@@ -340,7 +347,7 @@ static void pair_normalised(const okern *K, otri *t, double out[3]) {
     double amax = 0.0;
     for (int i = 0; i < t->nn; ++i) amax = fmax(amax, fabs(t->A[i]));
     octx c = {K, t, 12, 0, 4e-15 * fmax(1.0, (t->nn == 10 ? 3.0 : 1.0) * amax)};
-    double br[64];
+    double br[1024];
     int nb = 0;
     br[nb++] = -OR_PI;
     br[nb++] = OR_PI;
@@ -350,6 +357,27 @@ static void pair_normalised(const okern *K, otri *t, double out[3]) {
             for (int j = 0; j < 3; ++j)
                 if (j != i) br[nb++] = atan2(t->y[j], t->x[j]);
         }
+    }
+    /* directions in which a ray is parallel to an edge line, or hits it at
+     * the foot of the perpendicular: when the line passes close to the
+     * particle the integrand turns sharply within ~p radians of these, so
+     * they are made interval ends where the rules resolve the layer */
+    for (int e = 0; e < 3; ++e) {
+        br[nb++] = t->eang[e];
+        br[nb++] = t->eopp[e];
+        double fa = t->eang[e] + (t->ecr[e] > 0 ? -0.5 : 0.5) * OR_PI;
+        br[nb++] = wrap_pi(fa);
+        /* a line at distance p is met at r = p / sin(delta), delta the angle
+         * to its direction: the integrand depends on log(delta) for
+         * delta in [p, 1], so a geometric grading of breakpoints toward the
+         * parallel directions lets the rules see that layer */
+        double p = t->elen[e] > 0 ? fabs(t->ecr[e]) / t->elen[e] : 0.0;
+        if (p > 0.0 && p < 0.05)
+            for (double off = 0.25 * p; off < 0.2; off *= 2.0)
+                for (int sgn = -1; sgn <= 1; sgn += 2) {
+                    br[nb++] = wrap_pi(t->eang[e] + sgn * off);
+                    br[nb++] = wrap_pi(t->eopp[e] + sgn * off);
+                }
     }
     for (int p = 0; p < K->npieces; ++p) {
         double R = K->R[p];

@@ -220,7 +220,7 @@ def test_forward_orientation_independent():
     a = run_gpu(0, 1.0, np.zeros(n), np.zeros(n), tri, A, off, idx)
     b = run_gpu(0, 1.0, np.zeros(n), np.zeros(n), rev, Arev, off, idx)
     for k in range(3):
-        np.testing.assert_allclose(a[k], b[k], atol=1e-13)
+        np.testing.assert_allclose(a[k], b[k], rtol=0, atol=1e-12)
 
 
 def test_forward_deterministic():
@@ -241,7 +241,8 @@ def test_forward_full_size_covering_sampled():
     check_forward(wl, 2e-12, 2e-12, sample=np.sort(sel))
 
 
-def test_forward_slivers_sampled():
-    for kid in (0, 2, 3):
+def test_forward_slivers():
+    """Particles within 1e-8..1e-2 h of edges and vertices of 0.5-degree slivers."""
+    for kid in (0, 1, 2, 3):
         wl = W.sliver_stress(seed=3, grid=16, kernel=kid, field_order=0)
-        check_forward(wl, 1e-11, 1e-11)
+        check_forward(wl, 1e-12, 1e-12)

@@ -332,6 +332,12 @@ HARD = [
     # particle 4.7e-4 from an edge line
     [[0.6562608579813201, -0.4267303550543204], [0.6562608579813201, 2.4195307220231443],
      [-3.139159920024227, 2.0444958853791446]],
+    # sliver (0.5 degree angle) with its apex 1.2e-8 from the particle
+    [[1.2311630825934117e-08, 8.282441399387608e-10], [-0.4524655206795316, -0.32756939921435446],
+     [-0.44616864568845926, -0.3289828316068153]],
+    # sliver with a vertex 2.5e-7 from the particle
+    [[-0.13830074602240217, -1.9001834914084128], [2.854926606232766e-08, 2.5040686324473427e-07],
+     [-0.01671177609226504, -0.000810339688726458]],
 ]
 
 
