@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: particle-triangle pairs per second on one MI355X.
+
+Workload (the configuration the metric is quoted on): 1,048,576 particles on
+a jittered 1024^2 grid over [0,1]^2, support h = 2.5/1024, a 65,536-triangle
+covering boundary mesh with perturbed vertices (largest aspect ratio 20), a
+cubic Lagrange field (10 N(0,1) values per triangle) and the Wendland C2
+kernel.  Inputs are synthetic and seeded.
+
+A step is one evaluation of the closed-form integrals over all pairs (field
+records + pair kernel, FP64).  The pair list is built once beforehand and
+timed separately.  The JSON line also carries the dominant kernel's roofline
+position and the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------------------
+# algorithmic work model
+# ----------------------------------------------------------------------------
+def chebyshev_terms(n, kind):
+    """number of non-zero coefficients of T_n (kind 'T') or U_n (kind 'U')"""
+    if n < 0:
+        return 0
+    return n // 2 + 1
+
+
+def flop_model(deg, order):
+    """FP64 flops of the closed-form evaluation (FMA = 2, add/mul = 1).
+
+    Returns (per_pair, per_edge, per_triangle_part, per_clipped_end) for one
+    kernel piece; transcendental and division calls are not counted.
+    """
+    hmax, pmax = deg + order + 1, deg + order
+    nm = order + 1
+    # per pair: frame transform, orientation, Taylor shift of the field, harmonics, scaling
+    shift = sum((i + 1) * (m - i + 1) * 3 for m in range(order + 1) for i in range(m + 1))
+    per_pair = 12 + 5 + shift + 4 * nm + 6
+    # per edge: line geometry, rotation of the harmonics, rotation of the gradient back
+    harm_pairs = sum(len(range(m & 1, m + 1, 2)) for m in range(order + 1))
+    per_edge = 17 + 8 + 6 * harm_pairs + 6 + 3
+    # triangle part of one edge and piece
+    tri = 6 + 4 + 3 + 7 * (hmax - 1) + 4 * (pmax + 1)
+    for m in range(order + 1):
+        tri += 2 * ((m + 1) * (deg + 1) + m * (deg + 1) + (m + 2) * deg + (m + 1) * deg)
+        for n in range(m & 1, m + 1, 2):
+            tri += 2 * (chebyshev_terms(n, "T") + chebyshev_terms(n - 1, "U") + 2)
+        for n in range((m + 1) & 1, m + 2, 2):
+            tri += 2 * (chebyshev_terms(n, "T") + chebyshev_terms(n - 1, "U") + 4)
+        tri += 8 * (m + 1)            # harmonics of A_m cos, A_m sin
+    # sector part of one clipped end
+    clip = 10 + 12 * (order + 1)
+    for m in range(order + 1):
+        clip += 2 * 3 * (m + 2)
+    return per_pair, per_edge, tri, clip
+
+
+def edge_case_mix(px, py, tri, off, idx, h, radii):
+    """Counts of edges with a triangle part and of clipped edge ends over all pairs (torch, on the GPU)."""
+    import torch
+    N = px.numel()
+    owner = torch.repeat_interleave(torch.arange(N, device=px.device), off[1:] - off[:-1])
+    t = idx.long()
+    n_tri = 0
+    n_clip = 0
+    n_edges = 0
+    for e in range(3):
+        f = (e + 1) % 3
+        ax = (tri[2 * e][t] - px[owner]) / h
+        ay = (tri[2 * e + 1][t] - py[owner]) / h
+        bx = (tri[2 * f][t] - px[owner]) / h
+        by = (tri[2 * f + 1][t] - py[owner]) / h
+        lx, ly = bx - ax, by - ay
+        ln = torch.sqrt(lx * lx + ly * ly)
+        ok = ln > 0
+        sd = (ax * ly - ay * lx) / torch.where(ok, ln, torch.ones_like(ln))
+        p = sd.abs()
+        ok = ok & (p > 0)
+        ya = (ax * lx + ay * ly) / torch.where(ln > 0, ln, torch.ones_like(ln))
+        yb = ya + ln
+        n_edges += int(ok.sum())
+        for R in radii:
+            yc = torch.sqrt(torch.clamp(R * R - p * p, min=0.0))
+            n_tri += int((ok & (p < R)).sum())
+            n_clip += int((ok & (ya.abs() > yc)).sum()) + int((ok & (yb.abs() > yc)).sum())
+    return n_edges, n_tri, n_clip
+
+
+# ----------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n-side", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=16384, help="particles timed on the CPU oracle")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the pair kernel is measured on one device's share; "
+              "multi-GPU runs are not part of this benchmark.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2507_21686_amd as sb
+    from paper_2507_21686_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    log("bench: building workload")
+    nx, ny = 128 * args.n_side // 1024 or 1, 256 * args.n_side // 1024 or 1
+    wl = W.covering_workload(n_side=args.n_side, nx=nx, ny=ny, seed=2)
+    px = torch.tensor(wl.px, device=dev)
+    py = torch.tensor(wl.py, device=dev)
+    tri = torch.tensor(wl.tri, device=dev)
+    nodal = torch.tensor(wl.nodal, device=dev)
+    torch.cuda.synchronize()
+
+    log("bench: pair list")
+    t0 = time.perf_counter()
+    off, idx = sb.pairlist(px, py, tri, wl.h)
+    torch.cuda.synchronize()
+    pairlist_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    off, idx = sb.pairlist(px, py, tri, wl.h)          # second build, warm
+    torch.cuda.synchronize()
+    pairlist_ms_warm = (time.perf_counter() - t0) * 1e3
+    P = int(idx.numel())
+    N = wl.n_particles
+    T = wl.n_triangles
+    log(f"bench: N={N} T={T} pairs={P} ({P / N:.2f}/particle)")
+
+    integ = sb.Integrator(wl.kernel, wl.h, wl.n_nodes)
+    out = tuple(torch.empty(N, dtype=torch.float64, device=dev) for _ in range(3))
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        rec = integ.prepare(tri, nodal)
+        if ev is not None:
+            ev[0].record(stream)
+        integ.integrate_prepared(px, py, T, rec, off, idx, out=out)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    kern_ms = [a.elapsed_time(b) for a, b in evs]
+    kern_avg = float(np.mean(kern_ms))
+    log(f"bench: {ms_step:.3f} ms/step, pair kernel {kern_avg:.3f} ms (min {min(kern_ms):.3f})")
+
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("bench: copy probe 1 GiB x3 done")
+
+    # algorithmic work of one pair-kernel launch
+    kern = sb.kernel_preset(wl.kernel)
+    deg = max(kern.degree[p] for p in range(kern.n_pieces))
+    radii = [kern.radius[p] for p in range(kern.n_pieces)]
+    per_pair, per_edge, per_tri, per_clip = flop_model(deg, 3)
+    n_edges, n_tri, n_clip = edge_case_mix(px, py, tri, off, idx, wl.h, radii)
+    flops = P * per_pair + n_edges * per_edge + n_tri * per_tri + n_clip * per_clip
+    achieved = flops / (kern_avg * 1e-3) / 1e12
+    # algorithmic bytes: particles in/out, offsets, pair indices, triangle records (once)
+    alg_bytes = N * (16 + 24 + 8) + P * 4 + T * 128
+    log(f"bench: {flops / P:.0f} flop/pair (model), {achieved:.2f} TFLOP/s, "
+        f"{alg_bytes / (kern_avg * 1e-3) / 1e9:.1f} GB/s algorithmic")
+
+    result = {
+        "metric": "particle-triangle pairs/s (int W + int grad W)",
+        "value": P / (ms_step * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"covering mesh, {N} particles (jittered {args.n_side}^2 grid), {T} triangles "
+                               f"(max aspect ratio 20), cubic Lagrange field, Wendland C2, h=2.5/{args.n_side}",
+                   "particles": N, "triangles": T, "pairs": P, "field": "P3", "kernel": "wendland_c2",
+                   "precision": "fp64"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "forward_kernel", "kernel_ms": kern_avg, "flop_per_pair": flops / P,
+                     "alg_bytes_per_launch": alg_bytes},
+        "pairlist_ms": {"first": pairlist_ms, "warm": pairlist_ms_warm},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        nth = min(16, os.cpu_count() or 1)
+        rng = np.random.default_rng(0)
+        sel = np.sort(rng.choice(N, min(args.cpu_sample, N), replace=False))
+        off_h = off.cpu().numpy()
+        idx_h = idx.cpu().numpy()
+        soff = np.concatenate([[0], np.cumsum(off_h[sel + 1] - off_h[sel])])
+        sidx = np.concatenate([idx_h[off_h[i]:off_h[i + 1]] for i in sel])
+        log(f"bench: cpu oracle on {len(sel)} particles / {len(sidx)} pairs, {nth} threads")
+        t0 = time.perf_counter()
+        oracle.integrate(wl.kernel, wl.h, wl.px[sel], wl.py[sel], wl.tri, wl.nodal, soff, sidx, nthreads=nth)
+        dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.integrate(wl.kernel, wl.h, wl.px[sel], wl.py[sel], wl.tri, wl.nodal, soff, sidx, nthreads=nth,
+                         method="closed_form")
+        dt_cf = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": len(sidx) / dt, "unit": "pairs/s", "cores": nth, "kind": "oracle",
+                                  "sample": f"{len(sel)} random particles ({len(sidx)} pairs) of the same workload, "
+                                            f"definition oracle (adaptive polar quadrature), {nth} threads",
+                                  "closed_form_oracle_pairs_per_s": len(sidx) / dt_cf}
+        log(f"bench: cpu oracle {len(sidx) / dt:.3e} pairs/s (definition), {len(sidx) / dt_cf:.3e} (closed form)")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -147,6 +147,26 @@ int sphbi_integrate(const sphbi_kernel *kernel /* host */, const sphbi_opts *opt
                     int64_t n_pairs, double *I, double *Gx, double *Gy, double *per_pair, void *ws,
                     size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------
+ * The two stages of sphbi_integrate, for callers that reuse the per-triangle
+ * field records across calls (static boundary, repeated evaluation) or time
+ * the pair kernel alone.
+ *
+ * sphbi_field_prepare: writes T records of 16 doubles into rec (device,
+ * at least sphbi_integrate_workspace(T) bytes): the vertices and the field
+ * of every triangle as a polynomial about its first vertex (Sec. 3:
+ * barycentric / FEM-stencil fields are polynomials).  Asynchronous.
+ *
+ * sphbi_integrate_prepared: the pair kernel of sphbi_integrate on records
+ * written by sphbi_field_prepare with the same h and n_nodes.  Asynchronous.
+ * ------------------------------------------------------------------- */
+int sphbi_field_prepare(double h, int32_t n_nodes, int64_t T, const double *tri, const double *nodal, double *rec,
+                        size_t rec_bytes, void *stream);
+int sphbi_integrate_prepared(const sphbi_kernel *kernel /* host */, const sphbi_opts *opts /* host, NULL = default */,
+                             double h, int32_t n_nodes, int64_t N, const double *px, const double *py, int64_t T,
+                             const double *rec, const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs,
+                             double *I, double *Gx, double *Gy, double *per_pair, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

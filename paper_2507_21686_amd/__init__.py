@@ -22,7 +22,8 @@ FP64, MIXED = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENOWORKSPACE", -5: "ECAPACITY"}
 
 EXPORTS = ["sphbi_kernel_preset", "sphbi_default_opts", "sphbi_last_error", "sphbi_pairlist_plan",
-           "sphbi_pairlist_count", "sphbi_pairlist_fill", "sphbi_integrate_workspace", "sphbi_integrate"]
+           "sphbi_pairlist_count", "sphbi_pairlist_fill", "sphbi_integrate_workspace", "sphbi_integrate",
+           "sphbi_field_prepare", "sphbi_integrate_prepared"]
 
 
 class SphbiKernel(C.Structure):
@@ -67,6 +68,9 @@ def lib():
         L.sphbi_integrate_workspace.restype = C.c_size_t
         L.sphbi_integrate.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, i32, i64, vp, vp, i64, vp,
                                       vp, vp, vp, i64, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.sphbi_field_prepare.argtypes = [d, i32, i64, vp, vp, vp, C.c_size_t, vp]
+        L.sphbi_integrate_prepared.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, i32, i64, vp, vp,
+                                               i64, vp, vp, vp, i64, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -140,6 +144,35 @@ class Integrator:
         if self.ws is None or self.ws.numel() < need or self.ws.device != device:
             self.ws = torch.empty(need, dtype=torch.uint8, device=device)
         return self.ws
+
+    def prepare(self, tri, nodal):
+        """Per-triangle field records (the first stage); returns the record buffer."""
+        tri, nodal = _dev(tri), _dev(nodal)
+        T = tri.shape[1]
+        if nodal.shape[0] != self.n_nodes or nodal.shape[1] != T:
+            raise SphbiError("nodal must be [n_nodes, T]")
+        ws = self.workspace(T, tri.device)
+        _check(lib().sphbi_field_prepare(self.h, self.n_nodes, T, _ptr(tri), _ptr(nodal), _ptr(ws), ws.numel(),
+                                         _stream()), "sphbi_field_prepare")
+        return ws
+
+    def integrate_prepared(self, px, py, T, rec, offsets, tri_idx, per_pair: bool = False, out=None):
+        """Pair kernel on records from :meth:`prepare` (the second stage)."""
+        px, py = _dev(px), _dev(py)
+        offsets, tri_idx = _dev(offsets, torch.int64), _dev(tri_idx, torch.int32)
+        N, P = px.numel(), tri_idx.numel()
+        if out is None:
+            I = torch.empty(N, dtype=torch.float64, device=px.device)
+            Gx = torch.empty_like(I)
+            Gy = torch.empty_like(I)
+        else:
+            I, Gx, Gy = out
+        pp = torch.empty((3, P), dtype=torch.float64, device=px.device) if per_pair else None
+        _check(lib().sphbi_integrate_prepared(C.byref(self.kernel), C.byref(self.opts), self.h, self.n_nodes, N,
+                                              _ptr(px), _ptr(py), int(T), _ptr(rec), _ptr(offsets), _ptr(tri_idx), P,
+                                              _ptr(I), _ptr(Gx), _ptr(Gy), _ptr(pp), _stream()),
+               "sphbi_integrate_prepared")
+        return (I, Gx, Gy, pp) if per_pair else (I, Gx, Gy)
 
     def __call__(self, px, py, tri, nodal, offsets, tri_idx, per_pair: bool = False, out=None):
         px, py, tri, nodal = _dev(px), _dev(py), _dev(tri), _dev(nodal)

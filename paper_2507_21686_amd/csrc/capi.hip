@@ -462,20 +462,64 @@ size_t sphbi_integrate_workspace(int64_t T) {
     return (size_t)(T > 0 ? T : 1) * kRecDoubles * sizeof(double);
 }
 
-int sphbi_integrate(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,
-                    const double *px, const double *py, int64_t T, const double *tri, const double *nodal,
-                    const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, double *I, double *Gx,
-                    double *Gy, double *per_pair, void *ws, size_t ws_bytes, void *stream) {
+static int check_common(const sphbi_kernel *kernel, const sphbi_opts *opts, sphbi_opts *o, double h, int32_t n_nodes,
+                        int64_t N, int64_t T, int64_t n_pairs) {
     int rc = validate_kernel(kernel);
     if (rc) return rc;
-    sphbi_opts o;
-    sphbi_default_opts(&o);
-    if (opts) o = *opts;
-    if (o.precision != SPHBI_FP64 && o.precision != SPHBI_MIXED) { set_error("unknown precision %d", o.precision); return SPHBI_EINVAL; }
+    sphbi_default_opts(o);
+    if (opts) *o = *opts;
+    if (o->precision != SPHBI_FP64 && o->precision != SPHBI_MIXED) { set_error("unknown precision %d", o->precision); return SPHBI_EINVAL; }
     if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
     if (n_nodes != 1 && n_nodes != 3 && n_nodes != 10) { set_error("n_nodes must be 1, 3 or 10"); return SPHBI_EINVAL; }
     if (N < 0 || T < 0 || n_pairs < 0) { set_error("negative size"); return SPHBI_EINVAL; }
     if (T > INT32_MAX) { set_error("more than 2^31-1 triangles"); return SPHBI_EUNSUPPORTED; }
+    return SPHBI_OK;
+}
+
+int sphbi_field_prepare(double h, int32_t n_nodes, int64_t T, const double *tri, const double *nodal, double *rec,
+                        size_t rec_bytes, void *stream) {
+    if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
+    if (n_nodes != 1 && n_nodes != 3 && n_nodes != 10) { set_error("n_nodes must be 1, 3 or 10"); return SPHBI_EINVAL; }
+    if (T < 0) { set_error("negative size"); return SPHBI_EINVAL; }
+    if (T > INT32_MAX) { set_error("more than 2^31-1 triangles"); return SPHBI_EUNSUPPORTED; }
+    if (T == 0) return SPHBI_OK;
+    if (!tri || !nodal || !rec) { set_error("triangle/nodal/record arrays are NULL"); return SPHBI_EINVAL; }
+    if (!aligned8(tri) || !aligned8(nodal) || !aligned8(rec)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
+    if (rec_bytes < sphbi_integrate_workspace(T)) {
+        set_error("record buffer too small (%zu < %zu)", rec_bytes, sphbi_integrate_workspace(T));
+        return SPHBI_ENOWORKSPACE;
+    }
+    const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
+    return launch_prepare(order, T, tri, nodal, h, rec, (hipStream_t)stream);
+}
+
+int sphbi_integrate_prepared(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes,
+                             int64_t N, const double *px, const double *py, int64_t T, const double *rec,
+                             const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, double *I, double *Gx,
+                             double *Gy, double *per_pair, void *stream) {
+    sphbi_opts o;
+    int rc = check_common(kernel, opts, &o, h, n_nodes, N, T, n_pairs);
+    if (rc) return rc;
+    if (N > 0 && (!px || !py || !offsets || !I || !Gx || !Gy)) { set_error("particle arrays are NULL"); return SPHBI_EINVAL; }
+    if (n_pairs > 0 && (!tri_idx || !rec)) { set_error("pair/record arrays are NULL"); return SPHBI_EINVAL; }
+    const void *ptrs[] = {px, py, rec, offsets, tri_idx, I, Gx, Gy, per_pair};
+    for (const void *p : ptrs)
+        if (!aligned8(p)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
+    if (N == 0) return SPHBI_OK;
+    int deg = 0;
+    const KArgs K = make_kargs(kernel, &deg);
+    const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
+    return launch_forward(order, deg, o.precision, o.tau_edge, K, h, N, px, py, offsets, tri_idx, n_pairs, T, rec, I,
+                          Gx, Gy, per_pair, (hipStream_t)stream);
+}
+
+int sphbi_integrate(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,
+                    const double *px, const double *py, int64_t T, const double *tri, const double *nodal,
+                    const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, double *I, double *Gx,
+                    double *Gy, double *per_pair, void *ws, size_t ws_bytes, void *stream) {
+    sphbi_opts o;
+    int rc = check_common(kernel, opts, &o, h, n_nodes, N, T, n_pairs);
+    if (rc) return rc;
     if (N > 0 && (!px || !py || !offsets || !I || !Gx || !Gy)) { set_error("particle arrays are NULL"); return SPHBI_EINVAL; }
     if (n_pairs > 0 && (!tri_idx || !tri || !nodal)) { set_error("pair/triangle arrays are NULL"); return SPHBI_EINVAL; }
     const void *ptrs[] = {px, py, tri, nodal, offsets, tri_idx, I, Gx, Gy, per_pair, ws};
@@ -486,14 +530,10 @@ int sphbi_integrate(const sphbi_kernel *kernel, const sphbi_opts *opts, double h
         set_error("workspace too small (%zu < %zu)", ws_bytes, sphbi_integrate_workspace(T));
         return SPHBI_ENOWORKSPACE;
     }
-    int deg = 0;
-    const KArgs K = make_kargs(kernel, &deg);
-    const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
-    hipStream_t s = (hipStream_t)stream;
-    rc = launch_prepare(order, T, tri, nodal, h, (double *)ws, s);
+    rc = sphbi_field_prepare(h, n_nodes, T, tri, nodal, (double *)ws, ws_bytes, stream);
     if (rc) return rc;
-    return launch_forward(order, deg, o.precision, o.tau_edge, K, h, N, px, py, offsets, tri_idx, n_pairs, T,
-                          (const double *)ws, I, Gx, Gy, per_pair, s);
+    return sphbi_integrate_prepared(kernel, &o, h, n_nodes, N, px, py, T, (const double *)ws, offsets, tri_idx,
+                                    n_pairs, I, Gx, Gy, per_pair, stream);
 }
 
 }  // extern "C"
