@@ -33,6 +33,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per pair-kernel launch from the committed counter runs, or None.
+
+    The value (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration)
+    is only used while the kernel sources hash to what was profiled.
+    """
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "forward_kernel_covering_1M_p3_c2.json")
+    if not os.path.exists(prof):
+        return None
+    meta = json.load(open(prof))
+    h = hashlib.sha256()
+    for f in ("forward.hip", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2507_21686_amd", "csrc", f), "rb").read())
+    return meta["traffic_bytes_per_launch"] if h.hexdigest()[:16] == meta["source_sha256_16"] else None
+
+
 # ----------------------------------------------------------------------------
 # algorithmic work model
 # ----------------------------------------------------------------------------
@@ -213,7 +230,8 @@ def main():
                    "particles": N, "triangles": T, "pairs": P, "field": "P3", "kernel": "wendland_c2",
                    "precision": "fp64"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic() if args.n_side == 1024 else None,
                      "kernel": "forward_kernel", "kernel_ms": kern_avg, "flop_per_pair": flops / P,
                      "alg_bytes_per_launch": alg_bytes},
         "pairlist_ms": {"first": pairlist_ms, "warm": pairlist_ms_warm},
