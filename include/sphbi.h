@@ -167,6 +167,27 @@ int sphbi_integrate_prepared(const sphbi_kernel *kernel /* host */, const sphbi_
                              const double *rec, const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs,
                              double *I, double *Gx, double *Gy, double *per_pair, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Adjoint (vector-Jacobian product) of sphbi_integrate.
+ *
+ * Given cotangents gI, gGx, gGy [N] of the per-particle outputs, writes the
+ * gradients of L = sum_i gI_i I_i + gGx_i Gx_i + gGy_i Gy_i with respect to
+ *   dpx, dpy  [N]           particle positions,
+ *   dtri      [6][T]        triangle vertex coordinates (same layout as tri),
+ *   dnodal    [n_nodes][T]  nodal field values.
+ * The clipping and decomposition are recomputed, nothing is stored by the
+ * forward call.  Deterministic: triangle sums are taken in pair order.
+ * ws: device workspace of sphbi_integrate_backward_workspace(T, n_pairs,
+ * n_nodes) bytes.  FP64 only.  Asynchronous.
+ * ------------------------------------------------------------------- */
+size_t sphbi_integrate_backward_workspace(int64_t T, int64_t n_pairs, int32_t n_nodes);
+
+int sphbi_integrate_backward(const sphbi_kernel *kernel /* host */, const sphbi_opts *opts /* host, NULL = default */,
+                             double h, int32_t n_nodes, int64_t N, const double *px, const double *py, int64_t T,
+                             const double *tri, const double *nodal, const int64_t *offsets, const int32_t *tri_idx,
+                             int64_t n_pairs, const double *gI, const double *gGx, const double *gGy, double *dpx,
+                             double *dpy, double *dtri, double *dnodal, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENOWORK
 
 EXPORTS = ["sphbi_kernel_preset", "sphbi_default_opts", "sphbi_last_error", "sphbi_pairlist_plan",
            "sphbi_pairlist_count", "sphbi_pairlist_fill", "sphbi_integrate_workspace", "sphbi_integrate",
-           "sphbi_field_prepare", "sphbi_integrate_prepared"]
+           "sphbi_field_prepare", "sphbi_integrate_prepared", "sphbi_integrate_backward_workspace",
+           "sphbi_integrate_backward"]
 
 
 class SphbiKernel(C.Structure):
@@ -71,6 +72,11 @@ def lib():
         L.sphbi_field_prepare.argtypes = [d, i32, i64, vp, vp, vp, C.c_size_t, vp]
         L.sphbi_integrate_prepared.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, i32, i64, vp, vp,
                                                i64, vp, vp, vp, i64, vp, vp, vp, vp, vp]
+        L.sphbi_integrate_backward_workspace.argtypes = [i64, i64, i32]
+        L.sphbi_integrate_backward_workspace.restype = C.c_size_t
+        L.sphbi_integrate_backward.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, i32, i64, vp, vp,
+                                               i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp,
+                                               C.c_size_t, vp]
         _lib = L
     return _lib
 
@@ -193,6 +199,52 @@ class Integrator:
                                      _ptr(Gx), _ptr(Gy), _ptr(pp), _ptr(ws), ws.numel(), _stream()),
                "sphbi_integrate")
         return (I, Gx, Gy, pp) if per_pair else (I, Gx, Gy)
+
+
+def integrate_backward(kernel, h, px, py, tri, nodal, offsets, tri_idx, gI, gGx, gGy):
+    """Vector-Jacobian product of :func:`integrate`: (dpx, dpy, dtri [6,T], dnodal [n_nodes,T])."""
+    k = kernel_preset(kernel) if isinstance(kernel, int) else kernel
+    px, py, tri, nodal = _dev(px), _dev(py), _dev(tri), _dev(nodal)
+    gI, gGx, gGy = _dev(gI), _dev(gGx), _dev(gGy)
+    offsets, tri_idx = _dev(offsets, torch.int64), _dev(tri_idx, torch.int32)
+    N, T, P, nn = px.numel(), tri.shape[1], tri_idx.numel(), nodal.shape[0]
+    dpx = torch.empty_like(px)
+    dpy = torch.empty_like(py)
+    dtri = torch.empty_like(tri)
+    dnod = torch.empty_like(nodal)
+    need = int(lib().sphbi_integrate_backward_workspace(T, P, nn))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=px.device)
+    o = opts(FP64)
+    _check(lib().sphbi_integrate_backward(C.byref(k), C.byref(o), float(h), nn, N, _ptr(px), _ptr(py), T, _ptr(tri),
+                                          _ptr(nodal), _ptr(offsets), _ptr(tri_idx), P, _ptr(gI), _ptr(gGx),
+                                          _ptr(gGy), _ptr(dpx), _ptr(dpy), _ptr(dtri), _ptr(dnod), _ptr(ws),
+                                          ws.numel(), _stream()), "sphbi_integrate_backward")
+    return dpx, dpy, dtri, dnod
+
+
+class BoundaryIntegral(torch.autograd.Function):
+    """(I, Gx, Gy) = boundary integrals with gradients for px, py, tri and nodal.
+
+    forward(px, py, tri, nodal, offsets, tri_idx, kernel, h); the pair list is
+    treated as constant (it changes only where the kernel vanishes).
+    """
+
+    @staticmethod
+    def forward(ctx, px, py, tri, nodal, offsets, tri_idx, kernel, h):
+        ctx.save_for_backward(px, py, tri, nodal, offsets, tri_idx)
+        ctx.kernel, ctx.h = kernel, h
+        return integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx)
+
+    @staticmethod
+    def backward(ctx, gI, gGx, gGy):
+        px, py, tri, nodal, offsets, tri_idx = ctx.saved_tensors
+        z = torch.zeros_like(px)
+        gI = z if gI is None else gI.contiguous()
+        gGx = z if gGx is None else gGx.contiguous()
+        gGy = z if gGy is None else gGy.contiguous()
+        dpx, dpy, dtri, dnod = integrate_backward(ctx.kernel, ctx.h, px, py, tri, nodal, offsets, tri_idx,
+                                                  gI, gGx, gGy)
+        return dpx, dpy, dtri, dnod, None, None, None, None
 
 
 def integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx, per_pair=False, precision=FP64, tau_edge=1e-4):

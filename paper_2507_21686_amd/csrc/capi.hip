@@ -536,4 +536,37 @@ int sphbi_integrate(const sphbi_kernel *kernel, const sphbi_opts *opts, double h
                                     n_pairs, I, Gx, Gy, per_pair, stream);
 }
 
+size_t sphbi_integrate_backward_workspace(int64_t T, int64_t n_pairs, int32_t n_nodes) {
+    return backward_workspace(T > 0 ? T : 0, n_pairs > 0 ? n_pairs : 0, n_nodes == 10 ? 10 : (n_nodes == 3 ? 3 : 1));
+}
+
+int sphbi_integrate_backward(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes,
+                             int64_t N, const double *px, const double *py, int64_t T, const double *tri,
+                             const double *nodal, const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs,
+                             const double *gI, const double *gGx, const double *gGy, double *dpx, double *dpy,
+                             double *dtri, double *dnodal, void *ws, size_t ws_bytes, void *stream) {
+    sphbi_opts o;
+    int rc = check_common(kernel, opts, &o, h, n_nodes, N, T, n_pairs);
+    if (rc) return rc;
+    if (o.precision != SPHBI_FP64) { set_error("the adjoint runs in FP64 only"); return SPHBI_EUNSUPPORTED; }
+    if (n_pairs > INT32_MAX) { set_error("more than 2^31-1 pairs"); return SPHBI_EUNSUPPORTED; }
+    if (N > 0 && (!px || !py || !offsets || !gI || !gGx || !gGy || !dpx || !dpy)) {
+        set_error("particle arrays are NULL");
+        return SPHBI_EINVAL;
+    }
+    if (T > 0 && (!tri || !nodal || !dtri || !dnodal)) { set_error("triangle arrays are NULL"); return SPHBI_EINVAL; }
+    if (n_pairs > 0 && !tri_idx) { set_error("tri_idx is NULL"); return SPHBI_EINVAL; }
+    const void *ptrs[] = {px, py, tri, nodal, offsets, tri_idx, gI, gGx, gGy, dpx, dpy, dtri, dnodal, ws};
+    for (const void *p : ptrs)
+        if (!aligned8(p)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
+    const size_t need = backward_workspace(T, n_pairs, n_nodes);
+    if (!ws || ws_bytes < need) { set_error("workspace too small (%zu < %zu)", ws_bytes, need); return SPHBI_ENOWORKSPACE; }
+    int deg = 0;
+    const KArgs K = make_kargs(kernel, &deg);
+    const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
+    return launch_backward(order, deg, K, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, gI, gGx, gGy, dpx,
+                           dpy, dtri, dnodal, ws, (hipStream_t)stream);
+}
+
 }  // extern "C"
+

@@ -43,4 +43,10 @@ int launch_forward(int order, int deg, int precision, double tau_edge, const KAr
                    int64_t P, int64_t T, const double *rec, double *I, double *Gx, double *Gy, double *per_pair,
                    hipStream_t s);
 
+size_t backward_workspace(int64_t T, int64_t P, int n_nodes);
+int launch_backward(int order, int deg, const KArgs &K, double h, int64_t N, const double *px, const double *py,
+                    const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,
+                    const double *nodal, const double *gI, const double *gX, const double *gY, double *dpx,
+                    double *dpy, double *dtri, double *dnodal, void *ws, hipStream_t s);
+
 }  // namespace sphbi

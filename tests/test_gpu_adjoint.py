@@ -1,0 +1,177 @@
+"""GPU adjoint (vector-Jacobian product) against the oracle.
+
+* Leibniz: with cotangent gI = 1 the particle gradient is G itself
+  (eq. nablaIntegral is the x-derivative of eq. sphintegral).
+* Nodal gradients: the integrals are linear in the nodal values, so the
+  oracle gives them exactly from unit-field evaluations.
+* Vertex and particle gradients: 4th-order central differences of the
+  oracle (step 1e-3 h; truncation and oracle noise both near 1e-11).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2507_21686_amd as sb
+from paper_2507_21686_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+NTH = 16
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def setup(wl, seed=0):
+    t = [torch.as_tensor(np.ascontiguousarray(a), device=DEV) for a in (wl.px, wl.py, wl.tri, wl.nodal)]
+    off, idx = sb.pairlist(t[0], t[1], t[2], wl.h)
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((3, wl.n_particles))
+    tg = [torch.as_tensor(x, device=DEV) for x in g]
+    return t, off, idx, g, tg
+
+
+def owners(off):
+    return np.repeat(np.arange(len(off) - 1), np.diff(off))
+
+
+def loss_pairs(kid, h, wl, pairs, g, px=None, py=None, tri=None):
+    """sum over the given (particle, triangle) pairs of g . (I, Gx, Gy), by the oracle"""
+    px = wl.px if px is None else px
+    py = wl.py if py is None else py
+    tri = wl.tri if tri is None else tri
+    s = 0.0
+    for i, t in pairs:
+        o = oracle.pair(kid, h, px[i], py[i], tri[:, t], wl.nodal[:, t])
+        s += g[0][i] * o[0] + g[1][i] * o[1] + g[2][i] * o[2]
+    return s
+
+
+def fd4(f, e):
+    return (8 * (f(1) - f(-1)) - (f(2) - f(-2))) / (12 * e)
+
+
+def test_leibniz_particle_gradient_is_G():
+    wl = W.covering_workload(n_side=64, nx=8, ny=16, seed=4, kernel=1, field_order=3)
+    say("adjoint leibniz")
+    (px, py, tri, nod), off, idx, _, _ = setup(wl)
+    I, Gx, Gy = sb.integrate(wl.kernel, wl.h, px, py, tri, nod, off, idx)
+    one = torch.ones_like(px)
+    zero = torch.zeros_like(px)
+    dpx, dpy, _, _ = sb.integrate_backward(wl.kernel, wl.h, px, py, tri, nod, off, idx, one, zero, zero)
+    torch.cuda.synchronize()
+    scale = float(torch.abs(Gx).max())
+    # two code paths (dual-number derivative of I vs the closed form of G);
+    # Wendland C4 with a cubic field: kernel factor 1.1e3 times the P3 conditioning
+    assert float(torch.abs(dpx - Gx).max()) < 1e-10 * scale
+    assert float(torch.abs(dpy - Gy).max()) < 1e-10 * scale
+
+
+@pytest.mark.parametrize("kid,order", [(0, 0), (1, 3), (3, 1), (2, 3)])
+def test_vjp_against_oracle(kid, order):
+    wl = W.covering_workload(n_side=32, nx=4, ny=8, seed=4, kernel=kid, field_order=order)
+    say(f"adjoint vjp kid={kid} order={order}")
+    (px, py, tri, nod), off_t, idx_t, g, tg = setup(wl, seed=kid)
+    dpx, dpy, dtri, dnod = sb.integrate_backward(wl.kernel, wl.h, px, py, tri, nod, off_t, idx_t, *tg)
+    torch.cuda.synchronize()
+    dpx, dpy, dtri, dnod = [x.cpu().numpy() for x in (dpx, dpy, dtri, dnod)]
+    off, idx = off_t.cpu().numpy(), idx_t.cpu().numpy()
+    own = owners(off)
+    nn = wl.n_nodes
+    # nodal gradients: exact by linearity
+    ref_nod = np.zeros_like(wl.nodal)
+    for n in range(nn):
+        unit = np.zeros_like(wl.nodal)
+        unit[n] = 1.0
+        _, _, _, pp = oracle.integrate(kid, wl.h, wl.px, wl.py, wl.tri, unit, off, idx, per_pair=True, nthreads=NTH)
+        contrib = g[0][own] * pp[0] + g[1][own] * pp[1] + g[2][own] * pp[2]
+        ref_nod[n] = np.bincount(idx, weights=contrib, minlength=wl.n_triangles)
+    sc = np.abs(ref_nod).max()
+    kfac = {0: 141.0, 1: 1109.0, 2: 8704.0, 3: 30.0}[kid]      # monomial kernel cancellation
+    assert np.abs(dnod - ref_nod).max() <= 1e-13 * kfac * sc
+    # vertex gradients of sampled triangles: finite differences of the oracle
+    rng = np.random.default_rng(1)
+    e = 1e-3 * wl.h
+    tsel = rng.choice(wl.n_triangles, 12, replace=False)
+    worst = 0.0
+    for t in tsel:
+        pairs = [(own[q], t) for q in np.nonzero(idx == t)[0]]
+        for k in range(6):
+            def f(s):
+                tr = wl.tri.copy()
+                tr[k, t] += s * e
+                return loss_pairs(kid, wl.h, wl, pairs, g, tri=tr)
+            ref = fd4(f, e)
+            worst = max(worst, abs(dtri[k, t] - ref) / max(1.0, abs(ref)))
+    say(f"  vertex grad worst rel err {worst:.2e}")
+    assert worst < 3e-7          # finite-difference noise and truncation
+    # particle gradients of sampled particles
+    psel = rng.choice(np.nonzero(np.diff(off) > 0)[0], 12, replace=False)
+    worst = 0.0
+    for i in psel:
+        pairs = [(i, idx[q]) for q in range(off[i], off[i + 1])]
+        for comp, dref in ((0, dpx), (1, dpy)):
+            def f(s):
+                p2 = (wl.px if comp else wl.px.copy())
+                q2 = (wl.py.copy() if comp else wl.py)
+                if comp == 0:
+                    p2[i] += s * e
+                else:
+                    q2[i] += s * e
+                return loss_pairs(kid, wl.h, wl, pairs, g, px=p2, py=q2)
+            ref = fd4(f, e)
+            worst = max(worst, abs(dref[i] - ref) / max(1.0, abs(ref)))
+    say(f"  particle grad worst rel err {worst:.2e}")
+    assert worst < 3e-7
+
+
+def test_autograd_function_and_determinism():
+    wl = W.covering_workload(n_side=32, nx=4, ny=8, seed=4, kernel=1, field_order=3)
+    say("autograd")
+    (px, py, tri, nod), off, idx, g, tg = setup(wl)
+    leaves = [x.clone().requires_grad_(True) for x in (px, py, tri, nod)]
+    I, Gx, Gy = sb.BoundaryIntegral.apply(*leaves, off, idx, wl.kernel, wl.h)
+    loss = (I * tg[0] + Gx * tg[1] + Gy * tg[2]).sum()
+    loss.backward()
+    ref = sb.integrate_backward(wl.kernel, wl.h, px, py, tri, nod, off, idx, *tg)
+    ref2 = sb.integrate_backward(wl.kernel, wl.h, px, py, tri, nod, off, idx, *tg)
+    for leaf, r, r2 in zip(leaves, ref, ref2):
+        assert torch.equal(leaf.grad, r)
+        assert torch.equal(r, r2)
+
+
+def test_adjoint_full_size_sampled():
+    """512^2 particles, 16,384-triangle mesh, Wendland C4, P3; sampled FD checks."""
+    wl = W.covering_workload(n_side=512, nx=64, ny=128, seed=4, kernel=1, field_order=3)
+    say("adjoint full size")
+    (px, py, tri, nod), off_t, idx_t, g, tg = setup(wl, seed=7)
+    dpx, dpy, dtri, dnod = sb.integrate_backward(wl.kernel, wl.h, px, py, tri, nod, off_t, idx_t, *tg)
+    torch.cuda.synchronize()
+    dpx, dtri = dpx.cpu().numpy(), dtri.cpu().numpy()
+    off, idx = off_t.cpu().numpy(), idx_t.cpu().numpy()
+    own = owners(off)
+    say(f"  pairs={len(idx)}")
+    rng = np.random.default_rng(3)
+    e = 1e-3 * wl.h
+    worst = 0.0
+    for t in rng.choice(wl.n_triangles, 6, replace=False):
+        pairs = [(own[q], t) for q in np.nonzero(idx == t)[0]]
+        for k in (0, 3):
+            def f(s):
+                tr = wl.tri.copy()
+                tr[k, t] += s * e
+                return loss_pairs(wl.kernel, wl.h, wl, pairs, g, tri=tr)
+            ref = fd4(f, e)
+            worst = max(worst, abs(dtri[k, t] - ref) / max(1.0, abs(ref)))
+    for i in rng.choice(wl.n_particles, 6, replace=False):
+        pairs = [(i, idx[q]) for q in range(off[i], off[i + 1])]
+        def f(s):
+            p2 = wl.px.copy()
+            p2[i] += s * e
+            return loss_pairs(wl.kernel, wl.h, wl, pairs, g, px=p2)
+        ref = fd4(f, e)
+        worst = max(worst, abs(dpx[i] - ref) / max(1.0, abs(ref)))
+    say(f"  worst rel err {worst:.2e}")
+    assert worst < 1e-7
