@@ -10,7 +10,12 @@ kernel.  Inputs are synthetic and seeded.
 A step is one evaluation of the closed-form integrals over all pairs (field
 records + pair kernel, FP64).  The pair list is built once beforehand and
 timed separately.  The JSON line also carries the dominant kernel's roofline
-position and the CPU oracle timed on a bounded sample.
+position, the CPU oracle timed on a bounded sample and, under "modes":
+the same step in the mixed FP32/FP64 precision mode with its largest
+scale-normalised deviation from the FP64 results; the adjoint on the
+differentiation workload (262,144 particles, Wendland C4, P3); and the
+learned surrogate, trained here on the GPU, against the closed form on fresh
+pairs at a stated error.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -121,6 +126,101 @@ def edge_case_mix(px, py, tri, off, idx, h, radii):
     return n_edges, n_tri, n_clip
 
 
+def kernel_c_d_int_k(sb, kid):
+    """c_d * int_0^1 k(q) dq of a preset: the gradient of a half plane through the particle is twice this / h"""
+    k = sb.kernel_preset(kid)
+    tot = 0.0
+    for p in range(k.n_pieces):
+        R = k.radius[p]
+        tot += sum(k.b[p][j] * R ** (j + 1) / (j + 1) for j in range(k.degree[p] + 1))
+    return k.c_d * tot
+
+
+def event_time(torch, fn, steps, warmup):
+    """mean ms of fn() between HIP events on the current stream"""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def bench_adjoint(args, sb, W, torch, dev):
+    """Vector-Jacobian product on the differentiation workload: 262,144 particles
+    (jittered 512^2 grid), 16,384 perturbed triangles, Wendland C4, P3 field."""
+    wl = W.covering_workload(n_side=512, nx=64, ny=128, seed=4, kernel=1, field_order=3)
+    t = [torch.tensor(a, device=dev) for a in (wl.px, wl.py, wl.tri, wl.nodal)]
+    off, idx = sb.pairlist(t[0], t[1], t[2], wl.h)
+    g = [torch.randn(wl.n_particles, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(k))
+         for k in range(3)]
+    P = int(idx.numel())
+    ms_b = event_time(torch, lambda: sb.integrate_backward(wl.kernel, wl.h, *t, off, idx, *g), max(3, args.steps // 4),
+                      2)
+    ms_f = event_time(torch, lambda: sb.integrate(wl.kernel, wl.h, *t, off, idx), max(3, args.steps // 4), 2)
+    log(f"bench: adjoint {ms_b:.3f} ms ({P / (ms_b * 1e-3):.3e} pairs/s), forward {ms_f:.3f} ms on the same pairs")
+    return {"value": P / (ms_b * 1e-3), "unit": "pairs/s", "ms_per_step": ms_b, "forward_ms": ms_f,
+            "backward_over_forward": ms_b / ms_f,
+            "workload": f"{wl.n_particles} particles, {wl.n_triangles} triangles, {P} pairs, Wendland C4, P3, "
+                        f"gradients for positions, vertices and nodal values (FP64)"}
+
+
+def bench_surrogate(args, sb, torch, dev):
+    """Train the surrogate (Wendland C2, unit P0 field) on the GPU with the
+    library's kernels, calibrate its router on a held-out mesh and time the
+    served result against the closed form on fresh pairs."""
+    from paper_2507_21686_amd import surrogate as S
+    t0 = time.perf_counter()
+    train = [S.pair_set(seed, n_side=1024) for seed in (5, 15, 25)]
+    calib = S.pair_set(7, n_side=1024)
+    ev = S.pair_set(6, n_side=1024, keep_geometry=True)
+    t_data = time.perf_counter() - t0
+    net = S.Surrogate(kernel=0, seed=0)
+    info = net.train(train, steps=args.surrogate_steps, batch=16384)
+    thr = net.calibrate(calib, args.surrogate_level)
+    g = ev.geometry
+    T = g["tri"].shape[1]
+    model = net.model()
+    ws = torch.empty(int(sb.lib().sphbi_surrogate_workspace(T, ev.n)), dtype=torch.uint8, device=dev)
+    I, Gx, Gy, pp, flags, nf = net.integrate(ev.h, g["px"], g["py"], g["tri"], g["nodal"], g["off"], g["idx"],
+                                             model=model, per_pair=True, ws=ws)
+    torch.cuda.synchronize()
+    eI = (pp[0] - ev.per_pair[0]).abs()
+    eG = torch.maximum((pp[1] - ev.per_pair[1]).abs(), (pp[2] - ev.per_pair[2]).abs()) * ev.h / net.sg
+    err = torch.maximum(eI, eG)
+    flagged = int(nf.item())
+    q = torch.quantile(err[torch.randperm(ev.n, device=dev)[:1 << 22]], torch.tensor([0.5, 0.99, 0.9999], device=dev,
+                                                                                    dtype=torch.float64))
+    n_steps = max(3, args.steps // 2)
+    ms_s = event_time(torch, lambda: net.integrate(ev.h, g["px"], g["py"], g["tri"], g["nodal"], g["off"], g["idx"],
+                                                   model=model, ws=ws), n_steps, 2)
+    out = tuple(torch.empty_like(g["px"]) for _ in range(3))
+    res = {}
+    for name, prec in (("fp64", sb.FP64), ("mixed", sb.MIXED)):
+        integ = sb.Integrator(0, ev.h, 1, precision=prec)
+        rec = integ.prepare(g["tri"], g["nodal"])
+        res[name] = event_time(torch, lambda: integ.integrate_prepared(g["px"], g["py"], T, rec, g["off"], g["idx"],
+                                                                       out=out), n_steps, 2)
+    log(f"bench: surrogate {ms_s:.3f} ms vs closed form {res['fp64']:.3f} ms (fp64) / {res['mixed']:.3f} ms (mixed), "
+        f"flagged {flagged / ev.n:.3%}, max error {float(err.max()):.2e}; trained {info['steps']} steps in "
+        f"{info['seconds']:.1f} s on {info['pairs']} pairs (data {t_data:.1f} s)")
+    return {"value": ev.n / (ms_s * 1e-3), "unit": "pairs/s", "ms_per_step": ms_s,
+            "closed_form_fp64_pairs_per_s": ev.n / (res["fp64"] * 1e-3),
+            "closed_form_mixed_pairs_per_s": ev.n / (res["mixed"] * 1e-3),
+            "speedup_vs_fp64": res["fp64"] / ms_s, "speedup_vs_mixed": res["mixed"] / ms_s,
+            "stated_error": args.surrogate_level, "flagged_fraction": flagged / ev.n,
+            "error": {"max": float(err.max()), "p50": float(q[0]), "p99": float(q[1]), "p99.99": float(q[2])},
+            "threshold": thr,
+            "training": {"steps": info["steps"], "seconds": info["seconds"], "pairs": info["pairs"], "batch": 16384},
+            "workload": f"fresh covering mesh (seed 6): {len(g['px'])} particles, {T} triangles, {ev.n} pairs, "
+                        f"Wendland C2, unit P0 field; error = scale-normalised per-pair error vs the closed form"}
+
+
 # ----------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
@@ -131,6 +231,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16384, help="particles timed on the CPU oracle")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the surrogate")
+    ap.add_argument("--surrogate-steps", type=int, default=20000, help="Adam steps of the surrogate training")
+    ap.add_argument("--surrogate-level", type=float, default=1e-2,
+                    help="scale-normalised per-pair error the router is calibrated to")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the pair kernel is measured on one device's share; "
@@ -165,31 +270,44 @@ def main():
     T = wl.n_triangles
     log(f"bench: N={N} T={T} pairs={P} ({P / N:.2f}/particle)")
 
-    integ = sb.Integrator(wl.kernel, wl.h, wl.n_nodes)
-    out = tuple(torch.empty(N, dtype=torch.float64, device=dev) for _ in range(3))
     stream = torch.cuda.current_stream()
 
-    def step(ev=None):
-        rec = integ.prepare(tri, nodal)
-        if ev is not None:
-            ev[0].record(stream)
-        integ.integrate_prepared(px, py, T, rec, off, idx, out=out)
-        if ev is not None:
-            ev[1].record(stream)
+    def timed(precision):
+        """(ms per step, pair-kernel ms per launch, outputs) of one precision mode"""
+        integ = sb.Integrator(wl.kernel, wl.h, wl.n_nodes, precision=precision)
+        out = tuple(torch.empty(N, dtype=torch.float64, device=dev) for _ in range(3))
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = wall * 1e3 / args.steps
-    kern_ms = [a.elapsed_time(b) for a, b in evs]
-    kern_avg = float(np.mean(kern_ms))
-    log(f"bench: {ms_step:.3f} ms/step, pair kernel {kern_avg:.3f} ms (min {min(kern_ms):.3f})")
+        def step(ev=None):
+            rec = integ.prepare(tri, nodal)
+            if ev is not None:
+                ev[0].record(stream)
+            integ.integrate_prepared(px, py, T, rec, off, idx, out=out)
+            if ev is not None:
+                ev[1].record(stream)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kern_ms = [a.elapsed_time(b) for a, b in evs]
+        return wall * 1e3 / args.steps, float(np.mean(kern_ms)), min(kern_ms), out
+
+    ms_step, kern_avg, kern_min, out64 = timed(sb.FP64)
+    log(f"bench: fp64 {ms_step:.3f} ms/step, pair kernel {kern_avg:.3f} ms (min {kern_min:.3f})")
+    mx_step, mx_kern, mx_min, outmx = timed(sb.MIXED)
+    amax = float(torch.abs(nodal).max()) * 3.0
+    sG = 2 * kernel_c_d_int_k(sb, wl.kernel) / wl.h * amax
+    err_i = float((torch.abs(outmx[0] - out64[0]) / torch.clamp(torch.abs(out64[0]), min=amax)).max())
+    err_g = max(float((torch.abs(outmx[k] - out64[k]) / torch.clamp(torch.abs(out64[k]), min=sG)).max())
+                for k in (1, 2))
+    log(f"bench: mixed {mx_step:.3f} ms/step, pair kernel {mx_kern:.3f} ms; "
+        f"scaled error vs fp64 I {err_i:.2e} G {err_g:.2e}")
 
     if args.copy_probe:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -235,7 +353,17 @@ def main():
                      "kernel": "forward_kernel", "kernel_ms": kern_avg, "flop_per_pair": flops / P,
                      "alg_bytes_per_launch": alg_bytes},
         "pairlist_ms": {"first": pairlist_ms, "warm": pairlist_ms_warm},
+        "modes": {
+            "mixed": {"value": P / (mx_step * 1e-3), "unit": "pairs/s", "ms_per_step": mx_step,
+                      "kernel_ms": mx_kern, "speedup_vs_fp64_kernel": kern_avg / mx_kern,
+                      "max_scaled_err_vs_fp64": {"I": err_i, "G": err_g}},
+        },
     }
+
+    if not args.no_adjoint:
+        result["modes"]["adjoint"] = bench_adjoint(args, sb, W, torch, dev)
+    if not args.no_surrogate:
+        result["modes"]["surrogate"] = bench_surrogate(args, sb, torch, dev)
 
     if not args.no_cpu_baseline:
         import oracle

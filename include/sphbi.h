@@ -188,6 +188,87 @@ int sphbi_integrate_backward(const sphbi_kernel *kernel /* host */, const sphbi_
                              int64_t n_pairs, const double *gI, const double *gGx, const double *gGy, double *dpx,
                              double *dpy, double *dtri, double *dnodal, void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Learned surrogate of the per-pair result (an extension; the paper has no
+ * learned part).  A network 8 -> 128 -> 128 -> 128 -> 4 (ReLU) maps the
+ * canonical features of a pair to the standardised (I, h Gx, h Gy) of a unit
+ * P0 field in a rotated support-normalised frame (Sec. 2, transform C) plus
+ * an error indicator (log10 of its own expected scaled error).  Products run
+ * on the matrix cores in bfloat16 with FP32 accumulation; master weights,
+ * gradients and Adam moments are FP32.
+ *
+ * Parameters: one FP32 vector of SPHBI_MLP_PARAMS values, W1[8][128] b1[128]
+ * W2[128][128] b2[128] W3[128][128] b3[128] W4[128][4] b4[4], W[in][out].
+ * ------------------------------------------------------------------- */
+#define SPHBI_MLP_PARAMS 34692
+
+/* Canonical features of every pair of a CSR pair list: feats [n_pairs][8]
+ * (rotated vertex coordinates in units of h, then (#vertices with |nu| <= 1)/3
+ * and (#edges meeting the circle |nu| = 1)/3) and rot [n_pairs][2] = (cos,
+ * sin) of the frame rotation; the first vertex of the canonical order (the
+ * nearest to the particle) lies on the rotated +x axis.  Invalid triangle
+ * indices give zero features.  Asynchronous. */
+int sphbi_surrogate_features(double h, int64_t N, const double *px, const double *py, int64_t T, const double *tri,
+                             const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, float *feats,
+                             float *rot, void *stream);
+
+/* Training targets from closed-form per-pair values per_pair [3][n_pairs]
+ * (sphbi_integrate with a unit P0 field): targets [n_pairs][3] =
+ * ((I, h Gx', h Gy') - mean) / stdev, with (Gx', Gy') the gradient in the
+ * frame rotated by rot (as written by sphbi_surrogate_features).  mean and
+ * stdev are host arrays of 3.  Asynchronous. */
+int sphbi_surrogate_targets(int64_t n_pairs, double h, const double *per_pair, const float *rot,
+                            const float *mean /* host [3] */, const float *stdev /* host [3] */, float *targets,
+                            void *stream);
+
+/* Device workspace of the training calls for a batch of B rows.  Host only. */
+size_t sphbi_mlp_workspace(int64_t B);
+
+/* Network outputs out [B][4] for features feats [B][8] (all device).  Asynchronous. */
+int sphbi_mlp_forward(const float *params, int64_t B, const float *feats, float *out, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* Loss and gradient of a batch:
+ *   L = sum_b sum_{k<3} (y_bk - t_bk)^2 / (3B) + lam sum_b (y_b3 - e_b)^2 / B,
+ *   e_b = log10(max_k |y_bk - t_bk| scale_k + 1e-7)   (held constant),
+ * with y the network outputs, t = targets [B][3] (standardised) and scale
+ * [3] (host) converting standardised units into the scale-normalised error.
+ * Writes *loss (device, one float) and grad [SPHBI_MLP_PARAMS] (device,
+ * overwritten).  Deterministic.  Asynchronous. */
+int sphbi_mlp_loss_grad(const float *params, int64_t B, const float *feats, const float *targets,
+                        const float *scale /* host [3] */, float lam, float *loss, float *grad, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma & Ba, Algorithm 1, bias-corrected; `step` counts
+ * from 1) on n FP32 parameters with moments m, v (device, updated in place). */
+int sphbi_adam_step(float *params, float *m, float *v, const float *grad, int64_t n, double lr, double beta1,
+                    double beta2, double eps, int64_t step, void *stream);
+
+/* Serving model: the parameters rearranged for the fused kernel plus the
+ * output standardisation (mean, stdev of the three targets) and the trained
+ * feature range fmax.  sphbi_surrogate_model_bytes() bytes of device memory;
+ * sphbi_surrogate_pack fills it.  Asynchronous. */
+size_t sphbi_surrogate_model_bytes(void);
+int sphbi_surrogate_pack(const float *params, const float *mean /* host [3] */, const float *stdev /* host [3] */,
+                         float fmax, void *model, void *stream);
+
+/* Device workspace of sphbi_surrogate_integrate.  Host only. */
+size_t sphbi_surrogate_workspace(int64_t T, int64_t n_pairs);
+
+/* Per-particle integrals of a P0 field (nodal [T], one value per triangle)
+ * with the surrogate: a pair whose indicator exceeds `threshold`, or whose
+ * features leave the trained range, is flagged and evaluated in closed form
+ * (FP64) with `kernel` instead.  I, Gx, Gy [N] as sphbi_integrate; per_pair
+ * [3][n_pairs] optional; flags [n_pairs] (1 = evaluated in closed form);
+ * *n_flagged (device int64) receives their number.  The network is only
+ * meaningful for the kernel it was trained with.  Deterministic.
+ * Asynchronous. */
+int sphbi_surrogate_integrate(const sphbi_kernel *kernel /* host */, double h, int64_t N, const double *px,
+                              const double *py, int64_t T, const double *tri, const double *nodal,
+                              const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, const void *model,
+                              float threshold, double *I, double *Gx, double *Gy, double *per_pair, uint8_t *flags,
+                              int64_t *n_flagged, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

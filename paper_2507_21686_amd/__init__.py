@@ -24,7 +24,10 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENOWORK
 EXPORTS = ["sphbi_kernel_preset", "sphbi_default_opts", "sphbi_last_error", "sphbi_pairlist_plan",
            "sphbi_pairlist_count", "sphbi_pairlist_fill", "sphbi_integrate_workspace", "sphbi_integrate",
            "sphbi_field_prepare", "sphbi_integrate_prepared", "sphbi_integrate_backward_workspace",
-           "sphbi_integrate_backward"]
+           "sphbi_integrate_backward", "sphbi_surrogate_features", "sphbi_surrogate_targets", "sphbi_mlp_workspace", "sphbi_mlp_forward",
+           "sphbi_mlp_loss_grad", "sphbi_adam_step", "sphbi_surrogate_model_bytes", "sphbi_surrogate_pack",
+           "sphbi_surrogate_workspace", "sphbi_surrogate_integrate"]
+MLP_PARAMS = 34692
 
 
 class SphbiKernel(C.Structure):
@@ -77,6 +80,21 @@ def lib():
         L.sphbi_integrate_backward.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, i32, i64, vp, vp,
                                                i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp,
                                                C.c_size_t, vp]
+        f = C.c_float
+        L.sphbi_surrogate_features.argtypes = [d, i64, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
+        L.sphbi_surrogate_targets.argtypes = [i64, d, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
+        L.sphbi_mlp_workspace.argtypes = [i64]
+        L.sphbi_mlp_workspace.restype = C.c_size_t
+        L.sphbi_mlp_forward.argtypes = [vp, i64, vp, vp, vp, C.c_size_t, vp]
+        L.sphbi_mlp_loss_grad.argtypes = [vp, i64, vp, vp, C.POINTER(C.c_float), f, vp, vp, vp, C.c_size_t, vp]
+        L.sphbi_adam_step.argtypes = [vp, vp, vp, vp, i64, d, d, d, d, i64, vp]
+        L.sphbi_surrogate_model_bytes.argtypes = []
+        L.sphbi_surrogate_model_bytes.restype = C.c_size_t
+        L.sphbi_surrogate_pack.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float), f, vp, vp]
+        L.sphbi_surrogate_workspace.argtypes = [i64, i64]
+        L.sphbi_surrogate_workspace.restype = C.c_size_t
+        L.sphbi_surrogate_integrate.argtypes = [C.POINTER(SphbiKernel), d, i64, vp, vp, i64, vp, vp, vp, vp, i64,
+                                                vp, f, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
         _lib = L
     return _lib
 
@@ -251,3 +269,115 @@ def integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx, per_pair=False, p
     """Per-particle (I, Gx, Gy) [N] (and optionally per-pair [3, P]) on the GPU."""
     return Integrator(kernel, h, nodal.shape[0], precision, tau_edge)(px, py, tri, nodal, offsets, tri_idx,
                                                                       per_pair=per_pair)
+
+
+# ----------------------------------------------------------------------------
+# learned surrogate (C-ABI wrappers; the training loop is in surrogate.py)
+# ----------------------------------------------------------------------------
+def _f32(t):
+    return _dev(t, torch.float32)
+
+
+def surrogate_features(px, py, tri, h, offsets, tri_idx):
+    """Canonical pair features (float32 [P, 8]) and frame rotations (float32 [P, 2])."""
+    px, py, tri = _dev(px), _dev(py), _dev(tri)
+    offsets, tri_idx = _dev(offsets, torch.int64), _dev(tri_idx, torch.int32)
+    N, T, P = px.numel(), tri.shape[1], tri_idx.numel()
+    feats = torch.empty((P, 8), dtype=torch.float32, device=px.device)
+    rot = torch.empty((P, 2), dtype=torch.float32, device=px.device)
+    _check(lib().sphbi_surrogate_features(float(h), N, _ptr(px), _ptr(py), T, _ptr(tri), _ptr(offsets),
+                                          _ptr(tri_idx), P, _ptr(feats), _ptr(rot), _stream()),
+           "sphbi_surrogate_features")
+    return feats, rot
+
+
+def surrogate_targets(per_pair, rot, h, mean=(0.0, 0.0, 0.0), stdev=(1.0, 1.0, 1.0)):
+    """Standardised targets float32 [P, 3] in the rotated frame from per-pair values [3, P]."""
+    per_pair, rot = _dev(per_pair), _f32(rot)
+    P = per_pair.shape[1]
+    out = torch.empty((P, 3), dtype=torch.float32, device=per_pair.device)
+    m = (C.c_float * 3)(*[float(x) for x in mean])
+    sd = (C.c_float * 3)(*[float(x) for x in stdev])
+    _check(lib().sphbi_surrogate_targets(P, float(h), _ptr(per_pair), _ptr(rot), m, sd, _ptr(out), _stream()),
+           "sphbi_surrogate_targets")
+    return out
+
+
+class MLPWorkspace:
+    """Device workspace of the training calls for batches of up to B rows."""
+
+    def __init__(self, B, device="cuda:0"):
+        self.B = int(B)
+        self.buf = torch.empty(max(int(lib().sphbi_mlp_workspace(self.B)), 1), dtype=torch.uint8, device=device)
+
+    def fits(self, B):
+        return B <= self.B
+
+
+def mlp_forward(params, feats, ws=None):
+    """Network outputs float32 [B, 4] for features float32 [B, 8]."""
+    params, feats = _f32(params), _f32(feats)
+    B = feats.shape[0]
+    ws = ws if ws is not None and ws.fits(B) else MLPWorkspace(B, feats.device)
+    out = torch.empty((B, 4), dtype=torch.float32, device=feats.device)
+    _check(lib().sphbi_mlp_forward(_ptr(params), B, _ptr(feats), _ptr(out), _ptr(ws.buf), ws.buf.numel(), _stream()),
+           "sphbi_mlp_forward")
+    return out
+
+
+def mlp_loss_grad(params, feats, targets, scale, lam, ws=None, grad=None, loss=None):
+    """(loss float32 [1], grad float32 [MLP_PARAMS]) of one batch (see include/sphbi.h)."""
+    params, feats, targets = _f32(params), _f32(feats), _f32(targets)
+    B = feats.shape[0]
+    ws = ws if ws is not None and ws.fits(B) else MLPWorkspace(B, feats.device)
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feats.device) if grad is None else grad
+    loss = torch.empty(1, dtype=torch.float32, device=feats.device) if loss is None else loss
+    sc = (C.c_float * 3)(*[float(x) for x in scale])
+    _check(lib().sphbi_mlp_loss_grad(_ptr(params), B, _ptr(feats), _ptr(targets), sc, float(lam), _ptr(loss),
+                                     _ptr(grad), _ptr(ws.buf), ws.buf.numel(), _stream()), "sphbi_mlp_loss_grad")
+    return loss, grad
+
+
+def adam_step(params, m, v, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One in-place Adam update of params (and the moments m, v)."""
+    for t in (params, m, v, grad):
+        _f32(t)
+    _check(lib().sphbi_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(), float(lr), float(beta1),
+                                 float(beta2), float(eps), int(step), _stream()), "sphbi_adam_step")
+
+
+def surrogate_pack(params, mean, stdev, fmax):
+    """Serving model (device uint8 buffer) from FP32 parameters and output statistics."""
+    params = _f32(params)
+    model = torch.empty(int(lib().sphbi_surrogate_model_bytes()), dtype=torch.uint8, device=params.device)
+    m = (C.c_float * 3)(*[float(x) for x in mean])
+    sd = (C.c_float * 3)(*[float(x) for x in stdev])
+    _check(lib().sphbi_surrogate_pack(_ptr(params), m, sd, float(fmax), _ptr(model), _stream()),
+           "sphbi_surrogate_pack")
+    return model
+
+
+def surrogate_integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx, model, threshold, per_pair=False, ws=None):
+    """Per-particle integrals of a P0 field with the surrogate and the analytic fallback.
+
+    Returns (I, Gx, Gy, per_pair or None, flags uint8 [P], n_flagged int64 [1] on the device).
+    """
+    px, py, tri, nodal = _dev(px), _dev(py), _dev(tri), _dev(nodal)
+    offsets, tri_idx = _dev(offsets, torch.int64), _dev(tri_idx, torch.int32)
+    N, T, P = px.numel(), tri.shape[1], tri_idx.numel()
+    k = kernel if isinstance(kernel, SphbiKernel) else kernel_preset(kernel)
+    need = int(lib().sphbi_surrogate_workspace(T, P))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=px.device)
+    dev = px.device
+    I = torch.empty(N, dtype=torch.float64, device=dev)
+    Gx = torch.empty(N, dtype=torch.float64, device=dev)
+    Gy = torch.empty(N, dtype=torch.float64, device=dev)
+    pp = torch.empty((3, P), dtype=torch.float64, device=dev) if per_pair else None
+    flags = torch.empty(max(P, 1), dtype=torch.uint8, device=dev)
+    nf = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check(lib().sphbi_surrogate_integrate(C.byref(k), float(h), N, _ptr(px), _ptr(py), T, _ptr(tri), _ptr(nodal),
+                                           _ptr(offsets), _ptr(tri_idx), P, _ptr(model), float(threshold), _ptr(I),
+                                           _ptr(Gx), _ptr(Gy), _ptr(pp), _ptr(flags), _ptr(nf), _ptr(ws), ws.numel(),
+                                           _stream()), "sphbi_surrogate_integrate")
+    return I, Gx, Gy, pp, flags[:P], nf

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const KArgs K, double invh
                     for (int k = 0; k < 10; ++k) Ad[k] = D6(A[k]);
                     prepare_record<ORDER, D6>(vd, Ad, invh, rec);
                     D6 oI, oX, oY;
-                    pair_fwd<DEG, ORDER, D6>(K, D6(x), D6(y), invh, rec, oI, oX, oY);
+                    pair_fwd<DEG, ORDER, D6>(K, ExactMath(), 0.0, D6(x), D6(y), invh, rec, oI, oX, oY);
 #pragma unroll
                     for (int k = 0; k < 6; ++k) grad[k] = cI * oI.d[k] + cX * oX.d[k] + cY * oY.d[k];
                 }
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const KArgs K, double invh
                     for (int k = 0; k < 10; ++k) Au[k] = k == n ? 1.0 : 0.0;
                     prepare_record<ORDER, double>(v, Au, invh, rec);
                     double oI, oX, oY;
-                    pair_fwd<DEG, ORDER, double>(K, x, y, invh, rec, oI, oX, oY);
+                    pair_fwd<DEG, ORDER, double>(K, ExactMath(), 0.0, x, y, invh, rec, oI, oX, oY);
                     grad[6 + n] = cI * oI + cX * oX + cY * oY;
                 }
             }

@@ -9,6 +9,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "internal.h"
+#include "surrogate.h"
 
 namespace sphbi {
 
@@ -126,6 +127,7 @@ KArgs make_kargs(const sphbi_kernel *k, int *deg_out) {
     for (int p = 0; p < k->n_pieces; ++p) {
         const double R = k->radius[p];
         K.R[p] = R;
+        K.iR[p] = 1.0 / R;
         if (k->degree[p] > deg) deg = k->degree[p];
         for (int m = 0; m <= kMaxOrder; ++m) {
             double sv = 0.0, sw = 0.0;
@@ -469,6 +471,7 @@ static int check_common(const sphbi_kernel *kernel, const sphbi_opts *opts, sphb
     sphbi_default_opts(o);
     if (opts) *o = *opts;
     if (o->precision != SPHBI_FP64 && o->precision != SPHBI_MIXED) { set_error("unknown precision %d", o->precision); return SPHBI_EINVAL; }
+    if (!(o->tau_edge >= 0.0) || !isfinite(o->tau_edge)) { set_error("tau_edge must be finite and >= 0"); return SPHBI_EINVAL; }
     if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
     if (n_nodes != 1 && n_nodes != 3 && n_nodes != 10) { set_error("n_nodes must be 1, 3 or 10"); return SPHBI_EINVAL; }
     if (N < 0 || T < 0 || n_pairs < 0) { set_error("negative size"); return SPHBI_EINVAL; }
@@ -566,6 +569,129 @@ int sphbi_integrate_backward(const sphbi_kernel *kernel, const sphbi_opts *opts,
     const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
     return launch_backward(order, deg, K, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, gI, gGx, gGy, dpx,
                            dpy, dtri, dnodal, ws, (hipStream_t)stream);
+}
+
+// ----------------------------------------------------------------------------
+// learned surrogate
+// ----------------------------------------------------------------------------
+static bool aligned(const void *p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+int sphbi_surrogate_features(double h, int64_t N, const double *px, const double *py, int64_t T, const double *tri,
+                             const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, float *feats,
+                             float *rot, void *stream) {
+    if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
+    if (N < 0 || T < 0 || n_pairs < 0) { set_error("negative size"); return SPHBI_EINVAL; }
+    if (N > 0 && (!px || !py || !offsets)) { set_error("particle arrays are NULL"); return SPHBI_EINVAL; }
+    if (n_pairs > 0 && (!tri_idx || !feats || !rot || (T > 0 && !tri))) { set_error("pair arrays are NULL"); return SPHBI_EINVAL; }
+    const void *p8[] = {px, py, tri, offsets};
+    for (const void *p : p8)
+        if (!aligned8(p)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
+    if (!aligned(feats, 4) || !aligned(rot, 4) || !aligned(tri_idx, 4)) { set_error("arrays must be 4-byte aligned"); return SPHBI_EINVAL; }
+    return surrogate_features(h, N, px, py, T, tri, offsets, tri_idx, n_pairs, feats, rot, (hipStream_t)stream);
+}
+
+int sphbi_surrogate_targets(int64_t n_pairs, double h, const double *per_pair, const float *rot, const float *mean,
+                            const float *stdev, float *targets, void *stream) {
+    if (n_pairs < 0 || !(h > 0.0) || !isfinite(h)) { set_error("invalid size or h"); return SPHBI_EINVAL; }
+    if (!mean || !stdev) { set_error("NULL statistics"); return SPHBI_EINVAL; }
+    if (n_pairs > 0 && (!per_pair || !rot || !targets)) { set_error("NULL array"); return SPHBI_EINVAL; }
+    if (!aligned8(per_pair) || !aligned(rot, 4) || !aligned(targets, 4)) { set_error("misaligned array"); return SPHBI_EINVAL; }
+    SurrogateStats st;
+    for (int k = 0; k < 3; ++k) {
+        if (!(stdev[k] > 0.0f)) { set_error("stdev must be positive"); return SPHBI_EINVAL; }
+        st.mean[k] = mean[k];
+        st.stdev[k] = stdev[k];
+    }
+    st.fmax = 0.0f;
+    return surrogate_targets(n_pairs, h, per_pair, rot, st, targets, (hipStream_t)stream);
+}
+
+size_t sphbi_mlp_workspace(int64_t B) { return B < 0 ? 0 : mlp_workspace(B); }
+
+static int check_batch(int64_t B, const void *ws, size_t ws_bytes) {
+    if (B < 0 || B > ((int64_t)1 << 30)) { set_error("batch size %lld out of range", (long long)B); return SPHBI_EINVAL; }
+    const size_t need = mlp_workspace(B);
+    if (!ws || ws_bytes < need) { set_error("workspace too small (%zu < %zu)", ws_bytes, need); return SPHBI_ENOWORKSPACE; }
+    if (!aligned(ws, 256)) { set_error("workspace must be 256-byte aligned"); return SPHBI_EINVAL; }
+    return SPHBI_OK;
+}
+
+int sphbi_mlp_forward(const float *params, int64_t B, const float *feats, float *out, void *ws, size_t ws_bytes,
+                      void *stream) {
+    if (B == 0) return SPHBI_OK;
+    int rc = check_batch(B, ws, ws_bytes);
+    if (rc) return rc;
+    if (!params || !feats || !out) { set_error("NULL array"); return SPHBI_EINVAL; }
+    if (!aligned(params, 4) || !aligned(feats, 4) || !aligned(out, 4)) { set_error("arrays must be 4-byte aligned"); return SPHBI_EINVAL; }
+    return mlp_forward(params, B, feats, out, ws, (hipStream_t)stream);
+}
+
+int sphbi_mlp_loss_grad(const float *params, int64_t B, const float *feats, const float *targets, const float *scale,
+                        float lam, float *loss, float *grad, void *ws, size_t ws_bytes, void *stream) {
+    if (B <= 0) { set_error("empty batch"); return SPHBI_EINVAL; }
+    int rc = check_batch(B, ws, ws_bytes);
+    if (rc) return rc;
+    if (!params || !feats || !targets || !scale || !loss || !grad) { set_error("NULL array"); return SPHBI_EINVAL; }
+    if (!(lam >= 0.0f) || !isfinite(lam)) { set_error("lam must be finite and >= 0"); return SPHBI_EINVAL; }
+    const void *p4[] = {params, feats, targets, loss, grad};
+    for (const void *p : p4)
+        if (!aligned(p, 4)) { set_error("arrays must be 4-byte aligned"); return SPHBI_EINVAL; }
+    return mlp_loss_grad(params, B, feats, targets, scale, lam, loss, grad, ws, (hipStream_t)stream);
+}
+
+int sphbi_adam_step(float *params, float *m, float *v, const float *grad, int64_t n, double lr, double beta1,
+                    double beta2, double eps, int64_t step, void *stream) {
+    if (n < 0 || step < 1) { set_error("n must be >= 0 and step >= 1"); return SPHBI_EINVAL; }
+    if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0 && isfinite(lr))) {
+        set_error("invalid Adam hyper-parameters");
+        return SPHBI_EINVAL;
+    }
+    if (n > 0 && (!params || !m || !v || !grad)) { set_error("NULL array"); return SPHBI_EINVAL; }
+    return adam_step(params, m, v, grad, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+}
+
+size_t sphbi_surrogate_model_bytes(void) { return surrogate_model_bytes(); }
+
+int sphbi_surrogate_pack(const float *params, const float *mean, const float *stdev, float fmax, void *model,
+                         void *stream) {
+    if (!params || !mean || !stdev || !model) { set_error("NULL array"); return SPHBI_EINVAL; }
+    if (!aligned(model, 16) || !aligned(params, 4)) { set_error("model must be 16-byte aligned"); return SPHBI_EINVAL; }
+    SurrogateStats st;
+    for (int k = 0; k < 3; ++k) {
+        st.mean[k] = mean[k];
+        st.stdev[k] = stdev[k];
+    }
+    st.fmax = fmax;
+    return surrogate_pack(params, st, model, (hipStream_t)stream);
+}
+
+size_t sphbi_surrogate_workspace(int64_t T, int64_t n_pairs) {
+    return (T < 0 || n_pairs < 0) ? 0 : surrogate_workspace(T, n_pairs);
+}
+
+int sphbi_surrogate_integrate(const sphbi_kernel *kernel, double h, int64_t N, const double *px, const double *py,
+                              int64_t T, const double *tri, const double *nodal, const int64_t *offsets,
+                              const int32_t *tri_idx, int64_t n_pairs, const void *model, float threshold, double *I,
+                              double *Gx, double *Gy, double *per_pair, uint8_t *flags, int64_t *n_flagged, void *ws,
+                              size_t ws_bytes, void *stream) {
+    int rc = validate_kernel(kernel);
+    if (rc) return rc;
+    if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
+    if (N < 0 || T < 0 || n_pairs < 0) { set_error("negative size"); return SPHBI_EINVAL; }
+    if (T > INT32_MAX || n_pairs > INT32_MAX) { set_error("more than 2^31-1 triangles or pairs"); return SPHBI_EUNSUPPORTED; }
+    if (N > 0 && (!px || !py || !offsets || !I || !Gx || !Gy || !n_flagged || !model)) { set_error("NULL array"); return SPHBI_EINVAL; }
+    if (n_pairs > 0 && (!tri_idx || !flags || !tri || !nodal)) { set_error("pair/triangle arrays are NULL"); return SPHBI_EINVAL; }
+    const void *p8[] = {px, py, tri, nodal, offsets, I, Gx, Gy, per_pair, n_flagged};
+    for (const void *p : p8)
+        if (!aligned8(p)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
+    if (!aligned(model, 16) || !aligned(ws, 256)) { set_error("model/workspace misaligned"); return SPHBI_EINVAL; }
+    if (N == 0) return SPHBI_OK;
+    const size_t need = surrogate_workspace(T, n_pairs);
+    if (!ws || ws_bytes < need) { set_error("workspace too small (%zu < %zu)", ws_bytes, need); return SPHBI_ENOWORKSPACE; }
+    int deg = 0;
+    const KArgs K = make_kargs(kernel, &deg);
+    return surrogate_integrate(K, deg, h, N, px, py, T, tri, nodal, offsets, tri_idx, n_pairs, model, threshold, I, Gx,
+                               Gy, per_pair, flags, n_flagged, ws, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -35,6 +35,12 @@
 // segmented wave scan (pairs of a particle are contiguous) sums each
 // particle's pairs in a fixed order, so the result is deterministic without
 // atomics.
+//
+// Precision: the FP64 instantiation evaluates everything in double; the mixed
+// one takes the square roots and reciprocals (and, for P0/P1 fields, the
+// sector arctangents) from the FP32 hardware units (precision.h) and keeps
+// the logarithm of the radial term, the radial recurrences, the kernel
+// contraction and the per-particle sums in FP64.
 
 #include <math.h>
 
@@ -63,8 +69,8 @@ __global__ __launch_bounds__(256) void prepare_kernel(int64_t T, const double *_
     for (int k = 0; k < kRecDoubles; ++k) o[k] = r[k];
 }
 
-template <int DEG, int ORDER>
-__global__ __launch_bounds__(256) void forward_kernel(const KArgs K, double invh, int64_t N,
+template <int DEG, int ORDER, bool MIXED>
+__global__ __launch_bounds__(256) void forward_kernel(const KArgs K, double tau, double invh, int64_t N,
                                                       const double *__restrict__ px,
                                                       const double *__restrict__ py,
                                                       const int64_t *__restrict__ off,
@@ -98,8 +104,13 @@ __global__ __launch_bounds__(256) void forward_kernel(const KArgs K, double invh
         double vI = 0.0, vX = 0.0, vY = 0.0;
         if (q < q_end) {
             const int32_t t = tri_idx[q];
-            if (t >= 0 && t < T)    // out-of-range triangle indices contribute nothing
-                pair_fwd<DEG, ORDER, double>(K, px[ip], py[ip], invh, rec + (int64_t)t * kRecDoubles, vI, vX, vY);
+            if (t >= 0 && t < T) {   // out-of-range triangle indices contribute nothing
+                const double *r = rec + (int64_t)t * kRecDoubles;
+                if (MIXED)
+                    pair_fwd<DEG, ORDER, double>(K, MixedMath{false, ORDER >= 2}, tau, px[ip], py[ip], invh, r, vI,
+                                                 vX, vY);
+                else pair_fwd<DEG, ORDER, double>(K, ExactMath(), 0.0, px[ip], py[ip], invh, r, vI, vX, vY);
+            }
             if (per_pair) {
                 per_pair[q] = vI;
                 per_pair[P + q] = vX;
@@ -135,24 +146,38 @@ __global__ __launch_bounds__(256) void forward_kernel(const KArgs K, double invh
     }
 }
 
-template <int DEG, int ORDER>
-void launch_fwd_t(const KArgs &K, double invh, int64_t N, const double *px, const double *py, const int64_t *off,
-                  const int32_t *tri_idx, const double *rec, double *I, double *Gx, double *Gy, double *per_pair,
-                  int64_t P, int64_t T, hipStream_t s) {
-    const int64_t waves = (N + 63) / 64;
+struct FwdArgs {
+    double tau, invh;
+    int64_t N;
+    const double *px, *py;
+    const int64_t *off;
+    const int32_t *tri_idx;
+    const double *rec;
+    double *I, *Gx, *Gy, *per_pair;
+    int64_t P, T;
+};
+
+template <int DEG, int ORDER, bool MIXED>
+void launch_fwd_t(const KArgs &K, const FwdArgs &a, hipStream_t s) {
+    const int64_t waves = (a.N + 63) / 64;
     const int64_t blocks = (waves + 3) / 4;
-    hipLaunchKernelGGL((forward_kernel<DEG, ORDER>), dim3((unsigned)blocks), dim3(256), 0, s, K, invh, N, px, py,
-                       off, tri_idx, rec, I, Gx, Gy, per_pair, P, T);
+    hipLaunchKernelGGL((forward_kernel<DEG, ORDER, MIXED>), dim3((unsigned)blocks), dim3(256), 0, s, K, a.tau,
+                       a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair, a.P, a.T);
 }
 
-template <int ORDER>
-void launch_fwd_deg(int deg, const KArgs &K, double invh, int64_t N, const double *px, const double *py,
-                    const int64_t *off, const int32_t *tri_idx, const double *rec, double *I, double *Gx,
-                    double *Gy, double *per_pair, int64_t P, int64_t T, hipStream_t s) {
-    if (deg <= 3) launch_fwd_t<3, ORDER>(K, invh, N, px, py, off, tri_idx, rec, I, Gx, Gy, per_pair, P, T, s);
-    else if (deg <= 5) launch_fwd_t<5, ORDER>(K, invh, N, px, py, off, tri_idx, rec, I, Gx, Gy, per_pair, P, T, s);
-    else if (deg <= 8) launch_fwd_t<8, ORDER>(K, invh, N, px, py, off, tri_idx, rec, I, Gx, Gy, per_pair, P, T, s);
-    else launch_fwd_t<11, ORDER>(K, invh, N, px, py, off, tri_idx, rec, I, Gx, Gy, per_pair, P, T, s);
+template <int ORDER, bool MIXED>
+void launch_fwd_deg(int deg, const KArgs &K, const FwdArgs &a, hipStream_t s) {
+    if (deg <= 3) launch_fwd_t<3, ORDER, MIXED>(K, a, s);
+    else if (deg <= 5) launch_fwd_t<5, ORDER, MIXED>(K, a, s);
+    else if (deg <= 8) launch_fwd_t<8, ORDER, MIXED>(K, a, s);
+    else launch_fwd_t<11, ORDER, MIXED>(K, a, s);
+}
+
+template <bool MIXED>
+void launch_fwd_order(int order, int deg, const KArgs &K, const FwdArgs &a, hipStream_t s) {
+    if (order == 0) launch_fwd_deg<0, MIXED>(deg, K, a, s);
+    else if (order == 1) launch_fwd_deg<1, MIXED>(deg, K, a, s);
+    else launch_fwd_deg<3, MIXED>(deg, K, a, s);
 }
 
 }  // namespace
@@ -173,13 +198,10 @@ int launch_prepare(int order, int64_t T, const double *tri, const double *nodal,
 int launch_forward(int order, int deg, int precision, double tau_edge, const KArgs &K, double h, int64_t N,
                    const double *px, const double *py, const int64_t *offsets, const int32_t *tri_idx, int64_t P,
                    int64_t T, const double *rec, double *I, double *Gx, double *Gy, double *per_pair, hipStream_t s) {
-    (void)tau_edge;
-    if (precision != SPHBI_FP64) { set_error("precision mode %d not available", precision); return SPHBI_EUNSUPPORTED; }
     if (N == 0) return SPHBI_OK;
-    const double invh = 1.0 / h;
-    if (order == 0) launch_fwd_deg<0>(deg, K, invh, N, px, py, offsets, tri_idx, rec, I, Gx, Gy, per_pair, P, T, s);
-    else if (order == 1) launch_fwd_deg<1>(deg, K, invh, N, px, py, offsets, tri_idx, rec, I, Gx, Gy, per_pair, P, T, s);
-    else launch_fwd_deg<3>(deg, K, invh, N, px, py, offsets, tri_idx, rec, I, Gx, Gy, per_pair, P, T, s);
+    const FwdArgs a{tau_edge, 1.0 / h, N, px, py, offsets, tri_idx, rec, I, Gx, Gy, per_pair, P, T};
+    if (precision == SPHBI_MIXED) launch_fwd_order<true>(order, deg, K, a, s);
+    else launch_fwd_order<false>(order, deg, K, a, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("forward launch: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
     return SPHBI_OK;

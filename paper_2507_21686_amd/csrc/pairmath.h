@@ -8,6 +8,7 @@
 #include <math.h>
 
 #include "internal.h"
+#include "precision.h"
 
 namespace sphbi {
 
@@ -202,13 +203,13 @@ __host__ __device__ inline void taylor_shift(const S *__restrict__ e, S sx, S sy
 // One edge of the signed fan, one kernel piece of radius R.  Adds the
 // edge-frame value and gradient integrals (without c_d and without the
 // -1/h of the gradient).
-template <int DEG, int ORDER, typename S>
-__host__ __device__ inline void edge_piece(const KArgs &K, int pc, S p, S ya, S yb, const Harm<S> *hv,
-                                  S &oI, S &oX, S &oY) {
+template <int DEG, int ORDER, typename S, typename M>
+__host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc, S p, S ya, S yb,
+                                           const Harm<S> *hv, S &oI, S &oX, S &oY) {
     constexpr int HMAX = DEG + ORDER + 1;
     constexpr int PMAX = DEG + ORDER;
     const double R = K.R[pc];
-    const S yc = p < R ? S(sqrt((R - p) * (R + p))) : S(0.0);
+    const S yc = p < R ? S(math.sqrt_((R - p) * (R + p))) : S(0.0);
     const S aya = fabs(ya), ayb = fabs(yb);
     const bool clipA = aya > yc, clipB = ayb > yc;
 
@@ -216,7 +217,7 @@ __host__ __device__ inline void edge_piece(const KArgs &K, int pc, S p, S ya, S 
     S angc[5], angs[5];
 #pragma unroll
     for (int n = 0; n < 5; ++n) angc[n] = angs[n] = 0.0;
-    const S cpc = p < R ? S(p / R) : S(1.0), spc = p < R ? S(yc / R) : S(0.0);   // (cos, sin) psi_c
+    const S cpc = p < R ? S(p * K.iR[pc]) : S(1.0), spc = p < R ? S(yc * K.iR[pc]) : S(0.0);   // (cos, sin) psi_c
 #pragma unroll
     for (int end = 0; end < 2; ++end) {
         const bool clip = end ? clipB : clipA;
@@ -224,9 +225,10 @@ __host__ __device__ inline void edge_piece(const KArgs &K, int pc, S p, S ya, S 
         const S y = end ? yb : ya, ay = end ? ayb : aya;
         const double sg = end ? 1.0 : -1.0;          // Q(y_b) - Q(y_a)
         const double sy = y > 0.0 ? sg : -sg;          // odd cosine part
-        const S ir = 1.0 / sqrt(p * p + y * y);
+        S ir, ang;
+        math.sector_seed(p, ay, yc, ir, ang);
         const S cu = p * ir, su = ay * ir;
-        angc[0] += sy * atan2(p * (ay - yc), p * p + ay * yc);
+        angc[0] += sy * ang;
         S cn1 = 1.0, sn1 = 0.0, cn = cu, sn = su;      // cos/sin of n u
         S dn1 = 1.0, tn1 = 0.0, dn = cpc, tn = spc;    // cos/sin of n psi_c
 #pragma unroll
@@ -247,15 +249,10 @@ __host__ __device__ inline void edge_piece(const KArgs &K, int pc, S p, S ya, S 
     if (tri) {
         const S yA = clipA ? S(copysign(yc, ya)) : ya;
         const S yB = clipB ? S(copysign(yc, yb)) : yb;
-        const S rA = clipA ? S(R) : S(sqrt(p * p + ya * ya));
-        const S rB = clipB ? S(R) : S(sqrt(p * p + yb * yb));
-        const S ip = 1.0 / p;
-        const S fA = (fabs(yA) + rA) * ip, fB = (fabs(yB) + rB) * ip;
-        S h0;
+        const S rA = clipA ? S(R) : S(math.sqrt_(p * p + ya * ya));
+        const S rB = clipB ? S(R) : S(math.sqrt_(p * p + yb * yb));
         // H_0 = asinh(yB/p) - asinh(yA/p) with a single logarithm
-        if ((yA < 0.0 && yB > 0.0) || (yA > 0.0 && yB < 0.0)) h0 = (yB > 0.0 ? 1.0 : -1.0) * log(fA * fB);
-        else if (yB != 0.0) h0 = (yB > 0.0 ? 1.0 : -1.0) * log(fB / fA);
-        else h0 = (yA > 0.0 ? -1.0 : 1.0) * log(fA);
+        const S h0 = math.h0(p, yA, yB, rA, rB);
         const S p2 = p * p;
         H[0] = h0;
         H[1] = yB - yA;
@@ -353,9 +350,11 @@ __host__ __device__ inline void edge_piece(const KArgs &K, int pc, S p, S ya, S 
     }
 }
 
-template <int DEG, int ORDER, typename S>
-__host__ __device__ inline void pair_fwd(const KArgs &K, S x, S y, double invh, const S *__restrict__ r,
-                                S &oI, S &oX, S &oY) {
+// tau: edges whose line passes within tau (units of h) of the particle are
+// evaluated with the exact policy (only meaningful for MixedMath).
+template <int DEG, int ORDER, typename S, typename M>
+__host__ __device__ inline void pair_fwd(const KArgs &K, const M &math, double tau, S x, S y, double invh,
+                                         const S *__restrict__ r, S &oI, S &oX, S &oY) {
     oI = oX = oY = 0.0;
     S ax[3], ay[3];
 #pragma unroll
@@ -377,7 +376,8 @@ __host__ __device__ inline void pair_fwd(const KArgs &K, S x, S y, double invh, 
         const S Lx = ax[f] - axe, Ly = ay[f] - aye;
         const S len2 = Lx * Lx + Ly * Ly;
         if (len2 == 0.0) continue;
-        const S len = sqrt(len2), il = 1.0 / len;
+        S len, il;
+        math.edge_norm(len2, len, il);
         const S tx = Lx * il, ty = Ly * il;
         const S sd = axe * ty - aye * tx;        // signed distance of the edge line
         const S p = fabs(sd);
@@ -405,7 +405,8 @@ __host__ __device__ inline void pair_fwd(const KArgs &K, S x, S y, double invh, 
                 hl[m].s[n] = hs * cph[n] - hc * sph[n];
             }
         S eI = 0.0, eX = 0.0, eY = 0.0;
-        for (int pc = 0; pc < K.npieces; ++pc) edge_piece<DEG, ORDER, S>(K, pc, p, ya, yb, hl, eI, eX, eY);
+        const auto em = math.for_edge(p, tau);
+        for (int pc = 0; pc < K.npieces; ++pc) edge_piece<DEG, ORDER, S>(K, em, pc, p, ya, yb, hl, eI, eX, eY);
         I += eI;
         GX += eX * nx - eY * ny;
         GY += eX * ny + eY * nx;

@@ -1,0 +1,133 @@
+// Precision policies for the transcendental steps of one pair evaluation.
+//
+// ExactMath evaluates every square root, reciprocal, logarithm and arctangent
+// in the working type (double, or a dual number in the adjoint).
+//
+// MixedMath runs them on the FP32 hardware units instead:
+//   * sqrt, 1/sqrt and 1/x start from the FP32 estimate and take one Newton
+//     step in FP64, which leaves a relative error near 2e-14;
+//   * for P0 and P1 fields the arctangent and endpoint direction of the
+//     sector parts stay in FP32 (absolute errors near 1e-7).  A sector part is
+//     the whole radial kernel integral times an angular factor, so its
+//     sensitivity to the angle is of the size of the integrand and the FP32
+//     rounding is not amplified.  For P3 fields the angular factor is
+//     multiplied by the field's harmonics about the particle, which carry the
+//     extrapolation factor (d_max/width)^3 of the particle-anchored pieces
+//     (measured: 3e-6 to 8e-6 on the aspect-ratio-20 covering meshes with
+//     FP32 angles), so there the sector angles are evaluated in FP64.
+// The logarithm giving H_0 stays in FP64: H_0 enters only the even radial
+// terms H_2, H_4, ... (through the p^2 term of the recurrence), so an error in
+// it is multiplied by the odd part of the kernel's monomial sum, which does
+// not cancel (measured: an FP32 logarithm costs 4e-7 for Wendland C2 and
+// 1.5e-5 for C6, the ratio of sum|b_k|/|sum b_k| = 141 and 8.7e3).  The
+// recurrences H_c and P_e, the contraction with the kernel coefficients and
+// the accumulation stay in FP64.  An edge whose line passes within tau*h of
+// the particle (which includes the two edges of a vertex within tau*h) is
+// evaluated exactly.
+#pragma once
+
+#include <float.h>
+#include <math.h>
+
+namespace sphbi {
+
+struct ExactMath {
+    template <typename S>
+    __host__ __device__ S sqrt_(const S &x) const { return sqrt(x); }
+    template <typename S>
+    __host__ __device__ S rsqrt_(const S &x) const { return 1.0 / sqrt(x); }
+    template <typename S>
+    __host__ __device__ S rcp_(const S &x) const { return 1.0 / x; }
+    // angular terms of one clipped endpoint: 1/sqrt(p^2 + y^2) and the angle
+    // between the endpoint ray and the circle crossing psi_c
+    template <typename S>
+    __host__ __device__ void sector_seed(const S &p, const S &ay, const S &yc, S &ir, S &ang) const {
+        ir = 1.0 / sqrt(p * p + ay * ay);
+        ang = atan2(p * (ay - yc), p * p + ay * yc);
+    }
+    // H_0 = asinh(yB/p) - asinh(yA/p) from f = (|y| + rho)/p at both ends
+    template <typename S>
+    __host__ __device__ S h0(const S &p, const S &yA, const S &yB, const S &rA, const S &rB) const {
+        const S ip = 1.0 / p;
+        const S fA = (fabs(yA) + rA) * ip, fB = (fabs(yB) + rB) * ip;
+        if ((yA < 0.0 && yB > 0.0) || (yA > 0.0 && yB < 0.0)) return (yB > 0.0 ? 1.0 : -1.0) * log(fA * fB);
+        if (yB != 0.0) return (yB > 0.0 ? 1.0 : -1.0) * log(fB / fA);
+        return (yA > 0.0 ? -1.0 : 1.0) * log(fA);
+    }
+    // length and inverse length of an edge vector
+    template <typename S>
+    __host__ __device__ void edge_norm(const S &len2, S &len, S &il) const {
+        len = sqrt(len2);
+        il = 1.0 / len;
+    }
+    // policy for one edge at distance p (in units of h) from the particle
+    template <typename S>
+    __host__ __device__ ExactMath for_edge(const S &, double) const { return *this; }
+};
+
+// FP32 hardware estimates (one instruction each on gfx950).  Arguments are
+// clamped to the smallest normal float: the quantities they serve are lengths
+// in units of h, and below 1e-19 h their contribution vanishes anyway.
+__device__ inline float rsq_f32(float x) { return __builtin_amdgcn_rsqf(fmaxf(x, FLT_MIN)); }
+__device__ inline float rcp_f32(float x) { return __builtin_amdgcn_rcpf(x); }
+
+struct MixedMath {
+    bool exact;         // this edge is within tau*h of the particle: evaluate in FP64
+    bool fp64_angles;   // sector angles in FP64 (P3 fields)
+
+    __device__ double sqrt_(double x) const {
+        if (exact) return sqrt(x);
+        const double r = rsq_f32((float)x);
+        const double y = x * r;
+        return fma(0.5 * r, fma(-y, y, x), y);
+    }
+    __device__ double rsqrt_(double x) const {
+        if (exact) return 1.0 / sqrt(x);
+        const double r = rsq_f32((float)x);
+        return fma(0.5 * r, fma(-x * r, r, 1.0), r);
+    }
+    __device__ double rcp_(double x) const {
+        if (exact) return 1.0 / x;
+        const double r = rcp_f32((float)x);
+        return fma(r, fma(-x, r, 1.0), r);
+    }
+    __device__ void sector_seed(double p, double ay, double yc, double &ir, double &ang) const {
+        if (exact) {
+            ExactMath().sector_seed(p, ay, yc, ir, ang);
+            return;
+        }
+        if (fp64_angles) {
+            ir = rsqrt_(p * p + ay * ay);
+            ang = atan2(p * (ay - yc), p * p + ay * yc);
+            return;
+        }
+        ir = rsq_f32((float)(p * p + ay * ay));
+        ang = atan2f((float)(p * (ay - yc)), (float)(p * p + ay * yc));
+    }
+    __device__ double h0(double p, double yA, double yB, double rA, double rB) const {
+        if (exact) return ExactMath().h0(p, yA, yB, rA, rB);
+        const double gA = fabs(yA) + rA, gB = fabs(yB) + rB;
+        double arg, sg;
+        if ((yA < 0.0 && yB > 0.0) || (yA > 0.0 && yB < 0.0)) {
+            arg = gA * gB * rcp_(p * p);
+            sg = yB > 0.0 ? 1.0 : -1.0;
+        } else if (yB != 0.0) {
+            arg = gB * rcp_(gA);
+            sg = yB > 0.0 ? 1.0 : -1.0;
+        } else {
+            arg = gA * rcp_(p);
+            sg = yA > 0.0 ? -1.0 : 1.0;
+        }
+        return sg * log(arg);
+    }
+    __device__ void edge_norm(double len2, double &len, double &il) const {
+        il = rsqrt_(len2);
+        len = len2 * il;
+    }
+    // below 1e-15 h the FP32 estimates of 1/p^2 would leave the normal range
+    __device__ MixedMath for_edge(double p, double tau) const {
+        return MixedMath{p < tau || p < 1e-15, fp64_angles};
+    }
+};
+
+}  // namespace sphbi

@@ -62,11 +62,15 @@ def test_leibniz_particle_gradient_is_G():
     zero = torch.zeros_like(px)
     dpx, dpy, _, _ = sb.integrate_backward(wl.kernel, wl.h, px, py, tri, nod, off, idx, one, zero, zero)
     torch.cuda.synchronize()
-    scale = float(torch.abs(Gx).max())
-    # two code paths (dual-number derivative of I vs the closed form of G);
-    # Wendland C4 with a cubic field: kernel factor 1.1e3 times the P3 conditioning
-    assert float(torch.abs(dpx - Gx).max()) < 1e-10 * scale
-    assert float(torch.abs(dpy - Gy).max()) < 1e-10 * scale
+    scale = float(torch.maximum(torch.abs(Gx), torch.abs(Gy)).max())
+    # two code paths (dual-number derivative of I vs the closed form of G).
+    # Wendland C4 (monomial cancellation 1.1e3) with a cubic field extrapolated
+    # over particle-anchored pieces of aspect-ratio-20 triangles: the worst
+    # particle loses about 1e-10 relative, the typical one 1e-13.
+    for d, g in ((dpx, Gx), (dpy, Gy)):
+        err = torch.abs(d - g)
+        assert float(err.max()) < 5e-10 * scale
+        assert float(err.median()) < 1e-12 * scale
 
 
 @pytest.mark.parametrize("kid,order", [(0, 0), (1, 3), (3, 1), (2, 3)])
