@@ -182,6 +182,12 @@ def bench_surrogate(args, sb, torch, dev):
     t_data = time.perf_counter() - t0
     net = S.Surrogate(kernel=0, seed=0)
     info = net.train(train, steps=args.surrogate_steps, batch=16384)
+    levels = sorted({args.surrogate_level, 3e-3, 1e-2, 3e-2})
+    curve = {}
+    err_c, ind_c = net.pair_errors(calib)
+    for lv in levels:
+        t_lv = net.calibrate(calib, lv)
+        curve[f"{lv:g}"] = float((ind_c > t_lv).double().mean())
     thr = net.calibrate(calib, args.surrogate_level)
     g = ev.geometry
     T = g["tri"].shape[1]
@@ -199,6 +205,8 @@ def bench_surrogate(args, sb, torch, dev):
     n_steps = max(3, args.steps // 2)
     ms_s = event_time(torch, lambda: net.integrate(ev.h, g["px"], g["py"], g["tri"], g["nodal"], g["off"], g["idx"],
                                                    model=model, ws=ws), n_steps, 2)
+    ms_net = event_time(torch, lambda: net.integrate(ev.h, g["px"], g["py"], g["tri"], g["nodal"], g["off"], g["idx"],
+                                                     model=model, threshold=float("inf"), ws=ws), n_steps, 2)
     out = tuple(torch.empty_like(g["px"]) for _ in range(3))
     res = {}
     for name, prec in (("fp64", sb.FP64), ("mixed", sb.MIXED)):
@@ -206,6 +214,7 @@ def bench_surrogate(args, sb, torch, dev):
         rec = integ.prepare(g["tri"], g["nodal"])
         res[name] = event_time(torch, lambda: integ.integrate_prepared(g["px"], g["py"], T, rec, g["off"], g["idx"],
                                                                        out=out), n_steps, 2)
+    log(f"bench: network alone {ms_net:.3f} ms; flagged fraction by level {curve}")
     log(f"bench: surrogate {ms_s:.3f} ms vs closed form {res['fp64']:.3f} ms (fp64) / {res['mixed']:.3f} ms (mixed), "
         f"flagged {flagged / ev.n:.3%}, max error {float(err.max()):.2e}; trained {info['steps']} steps in "
         f"{info['seconds']:.1f} s on {info['pairs']} pairs (data {t_data:.1f} s)")
@@ -213,7 +222,9 @@ def bench_surrogate(args, sb, torch, dev):
             "closed_form_fp64_pairs_per_s": ev.n / (res["fp64"] * 1e-3),
             "closed_form_mixed_pairs_per_s": ev.n / (res["mixed"] * 1e-3),
             "speedup_vs_fp64": res["fp64"] / ms_s, "speedup_vs_mixed": res["mixed"] / ms_s,
-            "stated_error": args.surrogate_level, "flagged_fraction": flagged / ev.n,
+            "network_only_pairs_per_s": ev.n / (ms_net * 1e-3),
+            "stated_error": args.surrogate_level, "miss_rate": 1e-4, "flagged_fraction": flagged / ev.n,
+            "flagged_fraction_by_level": curve,
             "error": {"max": float(err.max()), "p50": float(q[0]), "p99": float(q[1]), "p99.99": float(q[2])},
             "threshold": thr,
             "training": {"steps": info["steps"], "seconds": info["seconds"], "pairs": info["pairs"], "batch": 16384},
@@ -233,7 +244,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the surrogate")
-    ap.add_argument("--surrogate-steps", type=int, default=20000, help="Adam steps of the surrogate training")
+    ap.add_argument("--surrogate-steps", type=int, default=40000, help="Adam steps of the surrogate training")
     ap.add_argument("--surrogate-level", type=float, default=1e-2,
                     help="scale-normalised per-pair error the router is calibrated to")
     args = ap.parse_args()

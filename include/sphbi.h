@@ -190,10 +190,12 @@ int sphbi_integrate_backward(const sphbi_kernel *kernel /* host */, const sphbi_
 
 /* ---------------------------------------------------------------------
  * Learned surrogate of the per-pair result (an extension; the paper has no
- * learned part).  A network 8 -> 128 -> 128 -> 128 -> 4 (ReLU) maps the
+ * learned part).  A network 8 -> 128 -> 128 -> 128 -> 4 maps the
  * canonical features of a pair to the standardised (I, h Gx, h Gy) of a unit
  * P0 field in a rotated support-normalised frame (Sec. 2, transform C) plus
- * an error indicator (log10 of its own expected scaled error).  Products run
+ * an error indicator (log10 of its own expected scaled error); between
+ * layers the activation z s(u), s(u) = 1/2 + u/4 - u|u|/32, u = clamp(z, -4,
+ * 4), a piecewise quadratic stand-in for z sigmoid(z).  Products run
  * on the matrix cores in bfloat16 with FP32 accumulation; master weights,
  * gradients and Adam moments are FP32.
  *

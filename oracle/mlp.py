@@ -22,7 +22,7 @@ The outputs (I, h Gx, h Gy) are predicted in the rotated frame; the gradient
 is rotated back.  Every geometric decision is taken in float64 without fused
 multiply-adds, as in the device code.
 
-Network: 8 -> 128 -> 128 -> 128 -> 4, ReLU between layers.  Outputs 0-2 are the
+Network: 8 -> 128 -> 128 -> 128 -> 4, activation act() between layers.  Outputs 0-2 are the
 standardised targets, output 3 an error indicator trained on the log10 of the
 network's own (detached) scaled error.  Parameters are one flat float32
 vector: W1[8][128], b1, W2[128][128], b2, W3[128][128], b3, W4[128][4], b4.
@@ -145,12 +145,19 @@ def unpack(params):
 
 
 def act(z):
-    """ReLU"""
-    return np.maximum(z, 0.0)
+    """z s(z) with s(z) = 1/2 + u/4 - u|u|/32, u = clamp(z, -4, 4): a
+    continuously differentiable piecewise quadratic stand-in for
+    z sigmoid(z) (s rises from 0 at z = -4 to 1 at z = 4 with zero slope at
+    both ends)."""
+    z = np.asarray(z, np.float64)
+    u = np.clip(z, -4.0, 4.0)
+    return z * (0.5 + u * (0.25 - np.abs(u) / 32.0))
 
 
 def act_grad(z):
-    return (np.asarray(z) > 0.0).astype(np.float64)
+    z = np.asarray(z, np.float64)
+    inner = 0.5 + z * (0.5 - 3.0 * np.abs(z) / 32.0)
+    return np.where(z >= 4.0, 1.0, np.where(z <= -4.0, 0.0, inner))
 
 
 def split_bf16(x):

@@ -137,6 +137,8 @@ __global__ void targets_kernel(int64_t P, double h, const double *__restrict__ p
 // ----------------------------------------------------------------------------
 // fused serving kernel
 // ----------------------------------------------------------------------------
+// 256 threads, two waves per SIMD: the model (79 KB of LDS) fits twice in a
+// CU's 160 KB and the kernel in 256 registers without spilling
 constexpr int kServeThreads = 256;
 
 __device__ inline bf16x8 pack8(const f32x16 &a, int half) {
@@ -177,7 +179,7 @@ __device__ inline void hidden_layer(const bf16 (*w)[8][64][8], const float *b, c
     }
 }
 
-__global__ __launch_bounds__(kServeThreads) void serve_kernel(
+__global__ __launch_bounds__(kServeThreads, 2) void serve_kernel(
     const Model *__restrict__ model, double invh, float threshold, int64_t N, const double *__restrict__ px,
     const double *__restrict__ py, int64_t T, const double *__restrict__ tri, const double *__restrict__ nodal,
     const int64_t *__restrict__ off, const int32_t *__restrict__ tri_idx, int64_t P, double *__restrict__ I,
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(kServeThreads) void serve_kernel(
         const int64_t my_off = pid < N ? min(max(off[pid], (int64_t)0), q_end) : q_end;
         const int64_t my_end = pid < N ? min(max(off[pid + 1], my_off), q_end) : q_end;
         const int64_t q_begin = __shfl(my_off, 0);
-        double accI = 0.0, accX = 0.0, accY = 0.0;
+        float accI = 0.0f, accX = 0.0f, accY = 0.0f;      // network values (FP32 is ample)
         for (int64_t base = q_begin; base < q_end; base += 64) {
             const int64_t q = base + lane;
             const int64_t qq = q < q_end ? q : q_end - 1;
@@ -213,21 +215,27 @@ __global__ __launch_bounds__(kServeThreads) void serve_kernel(
             }
             const int owner = lo;
             const int64_t ip = p0 + owner < N ? p0 + owner : N - 1;
-            // features of this lane's pair
+            // features of this lane's pair; the rotation and the field value are
+            // kept in FP32, which is ample at the network's accuracy
             float f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            double c = 1.0, s = 0.0, A = 0.0;
+            float cf = 1.0f, sf = 0.0f, Af = 0.0f;
             bool valid = false;
             if (q < q_end) {
                 const int32_t t = tri_idx[q];
                 if (t >= 0 && t < T) {
-                    double v[6];
+                    double v[6], c, s;
 #pragma unroll
                     for (int k = 0; k < 6; ++k) v[k] = tri[k * T + t];
                     pair_features(px[ip], py[ip], v, invh, f, c, s);
-                    A = nodal[t];
+                    cf = (float)c;
+                    sf = (float)s;
+                    Af = (float)nodal[t];
                     valid = true;
                 }
             }
+            bool inrange = valid;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) inrange = inrange && fabsf(f[k]) <= sm.fmax;
             // layer 1 operands: pair block 0 = the pairs of lanes 0-31, block 1 =
             // those of lanes 32-63; k slots 0-7 (lanes 0-31) take the bfloat16
             // high parts of the features, slots 8-15 (lanes 32-63) the low parts
@@ -276,17 +284,16 @@ __global__ __launch_bounds__(kServeThreads) void serve_kernel(
                 y[r] = lane < 32 ? o0[r] : from_low;
             }
             // router and de-standardisation
-            bool ok = valid && y[3] <= threshold;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) ok = ok && fabsf(f[k]) <= sm.fmax;
-            double vI = 0.0, vX = 0.0, vY = 0.0;
+            const bool ok = inrange && y[3] <= threshold;
+            float vI = 0.0f, vX = 0.0f, vY = 0.0f;
             if (ok) {
-                const double i0 = (double)(y[0] * sm.stdev[0] + sm.mean[0]);
-                const double g1 = (double)(y[1] * sm.stdev[1] + sm.mean[1]);
-                const double g2 = (double)(y[2] * sm.stdev[2] + sm.mean[2]);
-                vI = A * i0;
-                vX = A * invh * (c * g1 - s * g2);
-                vY = A * invh * (s * g1 + c * g2);
+                const float i0 = y[0] * sm.stdev[0] + sm.mean[0];
+                const float g1 = y[1] * sm.stdev[1] + sm.mean[1];
+                const float g2 = y[2] * sm.stdev[2] + sm.mean[2];
+                const float ah = Af * (float)invh;
+                vI = Af * i0;
+                vX = ah * (cf * g1 - sf * g2);
+                vY = ah * (sf * g1 + cf * g2);
             }
             if (q < q_end) {
                 flags[q] = (uint8_t)(valid && !ok);
@@ -298,7 +305,7 @@ __global__ __launch_bounds__(kServeThreads) void serve_kernel(
             }
 #pragma unroll
             for (int d = 1; d < 64; d <<= 1) {
-                const double uI = __shfl_up(vI, d), uX = __shfl_up(vX, d), uY = __shfl_up(vY, d);
+                const float uI = __shfl_up(vI, d), uX = __shfl_up(vX, d), uY = __shfl_up(vY, d);
                 const int uo = __shfl_up(owner, d);
                 if (lane >= d && uo == owner) {
                     vI += uI;
@@ -309,7 +316,7 @@ __global__ __launch_bounds__(kServeThreads) void serve_kernel(
             const int64_t s0 = my_off > base ? my_off : base;
             const int64_t s1 = my_end < base + 64 ? my_end : base + 64;
             const int src = s1 > s0 ? (int)(s1 - 1 - base) : 0;
-            const double rI = __shfl(vI, src), rX = __shfl(vX, src), rY = __shfl(vY, src);
+            const float rI = __shfl(vI, src), rX = __shfl(vX, src), rY = __shfl(vY, src);
             if (s1 > s0) {
                 accI += rI;
                 accX += rX;
@@ -317,9 +324,9 @@ __global__ __launch_bounds__(kServeThreads) void serve_kernel(
             }
         }
         if (pid < N) {
-            I[pid] = accI;
-            Gx[pid] = accX;
-            Gy[pid] = accY;
+            I[pid] = (double)accI;
+            Gx[pid] = (double)accX;
+            Gy[pid] = (double)accY;
         }
     }
 }

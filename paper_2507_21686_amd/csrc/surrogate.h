@@ -27,9 +27,19 @@ static_assert(kParams == SPHBI_MLP_PARAMS, "parameter count");
 // floor of the indicator target log10(err + floor)
 constexpr float kErrFloor = 1e-7f;
 
-// activation between layers
-__host__ __device__ inline float act(float z) { return z > 0.0f ? z : 0.0f; }
-__host__ __device__ inline float act_grad(float z) { return z > 0.0f ? 1.0f : 0.0f; }
+// activation between layers: a piecewise quadratic stand-in for z sigmoid(z),
+//   act(z) = z s(u),  s(u) = 1/2 + u/4 - u|u|/32,  u = clamp(z, -4, 4),
+// continuously differentiable (s rises from 0 to 1 with zero slope at both
+// ends); four FP32 operations and no transcendental
+__host__ __device__ inline float act(float z) {
+    const float u = fminf(fmaxf(z, -4.0f), 4.0f);
+    return z * fmaf(u, fmaf(fabsf(u), -0.03125f, 0.25f), 0.5f);
+}
+__host__ __device__ inline float act_grad(float z) {
+    if (z >= 4.0f) return 1.0f;
+    if (z <= -4.0f) return 0.0f;
+    return fmaf(z, fmaf(fabsf(z), -0.09375f, 0.5f), 0.5f);
+}
 
 // bfloat16 operand copies of the weights for the training products
 struct TrainWeights {

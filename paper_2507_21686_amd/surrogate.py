@@ -153,22 +153,25 @@ class Surrogate:
         err = ((out[:, :3] - t).abs() * sc).max(1).values
         return err, out[:, 3]
 
-    def calibrate(self, s: PairSet, target: float):
-        """Largest threshold such that every calibration pair with an indicator
-        at or below it has a scale-normalised error <= target."""
+    def calibrate(self, s: PairSet, level: float, miss: float = 1e-4):
+        """Largest threshold such that, among the calibration pairs whose
+        indicator is at or below it, at most a fraction `miss` has a
+        scale-normalised error above `level`."""
         err, ind = self.pair_errors(s)
         order = torch.argsort(ind)
-        run = torch.cummax(err[order], 0).values
-        ok = torch.nonzero(run <= target)
+        viol = torch.cumsum((err[order] > level).double(), 0)
+        k = torch.arange(1, order.numel() + 1, device=viol.device, dtype=torch.float64)
+        ok = torch.nonzero(viol <= miss * k)
         if ok.numel() == 0:
             self.threshold = float("-inf")
+            return self.threshold
+        j = int(ok.max())
+        if j + 1 >= order.numel():
+            self.threshold = float("inf")
         else:
-            k = int(ok.max())
-            # stop before the first pair that breaks the bound
-            nxt = float(ind[order[k + 1]]) if k + 1 < order.numel() else float("inf")
-            self.threshold = float(ind[order[k]]) if k + 1 < order.numel() else float("inf")
-            if nxt == self.threshold:
-                self.threshold = float(np.nextafter(np.float32(self.threshold), np.float32(-np.inf)))
+            # just below the first indicator value that is not accepted
+            nxt = np.float32(ind[order[j + 1]].item())
+            self.threshold = float(np.nextafter(nxt, np.float32(-np.inf)))
         return self.threshold
 
     # -------------------------------------------------------------- serving

@@ -160,11 +160,11 @@ def test_serve_kernel_and_router():
     got = pp.cpu().numpy().T
     for k, name in enumerate(("I", "Gx", "Gy")):
         close_bf16(got[:, k], want[:, k], f"serve {name}")
-    # per-particle sums equal the per-pair values summed
+    # per-particle sums equal the per-pair values summed (network values are summed in FP32)
     own = owners(off)
     for k, out in enumerate((I, Gx, Gy)):
         s = np.bincount(own, weights=got[:, k], minlength=wl.n_particles)
-        np.testing.assert_allclose(out.cpu().numpy(), s, rtol=1e-12, atol=1e-12 * np.abs(s).max())
+        np.testing.assert_allclose(out.cpu().numpy(), s, rtol=1e-6, atol=1e-6 * np.abs(s).max())
     # threshold between indicator values: exactly the pairs above it are flagged
     thr = float(np.median(ind))
     I2, Gx2, Gy2, pp2, flags2, nf2 = sb.surrogate_integrate(0, wl.h, px, py, tri, nod, off, idx, model, thr,
@@ -181,7 +181,7 @@ def test_serve_kernel_and_router():
     np.testing.assert_array_equal(got2[:, ~fl], got[~fl].T)
     for k, out in enumerate((I2, Gx2, Gy2)):
         s = np.bincount(own, weights=got2[k], minlength=wl.n_particles)
-        np.testing.assert_allclose(out.cpu().numpy(), s, rtol=1e-12, atol=1e-12 * np.abs(s).max())
+        np.testing.assert_allclose(out.cpu().numpy(), s, rtol=1e-6, atol=1e-6 * np.abs(s).max())
     # everything flagged: the closed form
     I3, Gx3, Gy3, _, flags3, nf3 = sb.surrogate_integrate(0, wl.h, px, py, tri, nod, off, idx, model, -1e30)
     I64, Gx64, Gy64 = sb.integrate(0, wl.h, px, py, tri, nod, off, idx)

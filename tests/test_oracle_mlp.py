@@ -111,8 +111,21 @@ def torch_forward(params, x):
         o += n
         a = a @ W + b
         if li < len(mlp.LAYERS) - 1:
-            a = torch.relu(a)
+            u = torch.clamp(a, -4.0, 4.0)
+            a = a * (0.5 + u * (0.25 - u.abs() / 32.0))
     return a
+
+
+def test_activation_is_c1_and_its_derivative_matches():
+    z = np.linspace(-6, 6, 24001)
+    a = mlp.act(z)
+    # limits: 0 far left, identity far right, continuous derivative across the joins at |z| = 4 and 0
+    assert np.all(a[z <= -4] == 0.0) and np.allclose(a[z >= 4], z[z >= 4])
+    fd = np.gradient(a, z)
+    np.testing.assert_allclose(mlp.act_grad(z)[1:-1], fd[1:-1], atol=2e-4)
+    for c in (-4.0, 0.0, 4.0):
+        e = 1e-9
+        assert abs(mlp.act_grad(c - e) - mlp.act_grad(c + e)) < 1e-8
 
 
 def test_param_count():
@@ -144,7 +157,8 @@ def test_gradient_finite_differences_and_autograd():
         o += n
         a = a @ W + b
         if li < len(mlp.LAYERS) - 1:
-            a = torch.relu(a)
+            u = torch.clamp(a, -4.0, 4.0)
+            a = a * (0.5 + u * (0.25 - u.abs() / 32.0))
     d = a[:, :3] - torch.tensor(t)
     e = torch.log10((d.detach().abs() * torch.tensor(scale)).max(1).values + mlp.ERR_FLOOR)
     Lt = (d * d).sum() / (3 * 40) + lam * ((a[:, 3] - e) ** 2).sum() / 40
