@@ -31,6 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+BF16_MFMA_PEAK_TFLOPS = 2500.0      # dense BF16 matrix-core peak of MI355X
+# algorithmic flops of one network evaluation: 2 (8*128 + 128*128 + 128*128 + 128*4)
+MLP_FLOPS_PER_PAIR = 2 * (8 * 128 + 128 * 128 + 128 * 128 + 128 * 4)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -50,7 +53,7 @@ def measured_traffic():
         return None
     meta = json.load(open(prof))
     h = hashlib.sha256()
-    for f in ("forward.hip", "internal.h"):
+    for f in meta["source_files"]:
         h.update(open(os.path.join(ROOT, "paper_2507_21686_amd", "csrc", f), "rb").read())
     return meta["traffic_bytes_per_launch"] if h.hexdigest()[:16] == meta["source_sha256_16"] else None
 
@@ -223,6 +226,11 @@ def bench_surrogate(args, sb, torch, dev):
             "closed_form_mixed_pairs_per_s": ev.n / (res["mixed"] * 1e-3),
             "speedup_vs_fp64": res["fp64"] / ms_s, "speedup_vs_mixed": res["mixed"] / ms_s,
             "network_only_pairs_per_s": ev.n / (ms_net * 1e-3),
+            "roofline": {"bound": "mfma", "kernel": "serve_kernel",
+                         "achieved": MLP_FLOPS_PER_PAIR * ev.n / (ms_net * 1e-3) / 1e12, "peak": BF16_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s",
+                         "frac": MLP_FLOPS_PER_PAIR * ev.n / (ms_net * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS,
+                         "flop_per_pair": MLP_FLOPS_PER_PAIR},
             "stated_error": args.surrogate_level, "miss_rate": 1e-4, "flagged_fraction": flagged / ev.n,
             "flagged_fraction_by_level": curve,
             "error": {"max": float(err.max()), "p50": float(q[0]), "p99": float(q[1]), "p99.99": float(q[2])},

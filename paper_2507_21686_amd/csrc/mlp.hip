@@ -215,14 +215,22 @@ __global__ __launch_bounds__(256) void sum_kernel(const float *__restrict__ part
     if (threadIdx.x == 0) out[0] = red[0];
 }
 
-// column sums of dz [M][N] over row chunks: part[z][n]
-__global__ void colsum_kernel(const bf16 *__restrict__ dz, int64_t M, int N, int64_t rows, float *__restrict__ part) {
-    const int n = threadIdx.x;
-    if (n >= N) return;
-    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(M, r0 + rows);
+// column sums of dz [M][N] over chunks of kColRows rows: part[z][n].  A block
+// covers 64 columns; its four waves take every fourth row of the chunk and
+// are combined in a fixed order (deterministic).
+constexpr int kColRows = 256;
+__global__ __launch_bounds__(256) void colsum_kernel(const bf16 *__restrict__ dz, int64_t M, int N,
+                                                     float *__restrict__ part) {
+    __shared__ float red[4][64];
+    const int l = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int n = blockIdx.y * 64 + l;
+    const int64_t r0 = (int64_t)blockIdx.x * kColRows, r1 = min(M, r0 + kColRows);
     float s = 0.0f;
-    for (int64_t m = r0; m < r1; ++m) s += (float)dz[m * N + n];
-    part[(int64_t)blockIdx.x * N + n] = s;
+    if (n < N)
+        for (int64_t m = r0 + ph; m < r1; m += 4) s += (float)dz[m * N + n];
+    red[ph][l] = s;
+    __syncthreads();
+    if (ph == 0 && n < N) part[(int64_t)blockIdx.x * N + n] = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
 }
 
 // grad[off + k n_real + n] = sum_z part[z][k][n] (+ part[z][k + fold][n]) for
@@ -278,7 +286,7 @@ struct TrainWs {
     bf16 *dz4;                  // [Bp][32]
     bf16 *dz[3];                // [Bp][128]  (dz of hidden layers 1..3)
     float *wpart;               // [splits][128][128]
-    float *bpart;               // [splits][128]
+    float *bpart;               // [Bp / kColRows + 1][128]
     float *lpart;               // [Bp / 256 + 1]
     size_t bytes;
 };
@@ -307,7 +315,7 @@ TrainWs carve(void *base, int64_t B) {
     t.dz4 = (bf16 *)take(Bp * 32 * 2);
     for (int l = 0; l < 3; ++l) t.dz[l] = (bf16 *)take(Bp * 128 * 2);
     t.wpart = (float *)take(splits * 128 * 128 * 4);
-    t.bpart = (float *)take(splits * 128 * 4);
+    t.bpart = (float *)take((Bp / kColRows + 1) * 128 * 4);
     t.lpart = (float *)take((Bp / 256 + 1) * 4);
     t.bytes = o;
     return t;
@@ -391,9 +399,10 @@ int mlp_loss_grad(const float *params, int64_t B, const float *feats, const floa
         gemm<false, false, EPI_PART>(g, splits, s);
         hipLaunchKernelGGL(reduce_w_kernel, dim3((unsigned)((kreal[l] * nreal[l] + 255) / 256)), dim3(256), 0, s,
                            t.wpart, splits, K, N, kreal[l], nreal[l], l == 0 ? kIn : 0, grad + offw[l]);
-        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)splits), dim3(128), 0, s, dz_top[l], Bp, N,
-                           (int64_t)kRowsPerSplit, t.bpart);
-        hipLaunchKernelGGL(reduce_b_kernel, dim3(1), dim3(128), 0, s, t.bpart, splits, N, nreal[l], grad + offb[l]);
+        const int csplits = (int)((Bp + kColRows - 1) / kColRows);
+        hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)csplits, (unsigned)((N + 63) / 64)), dim3(256), 0, s,
+                           dz_top[l], Bp, N, t.bpart);
+        hipLaunchKernelGGL(reduce_b_kernel, dim3(1), dim3(128), 0, s, t.bpart, csplits, N, nreal[l], grad + offb[l]);
         if (l == 0) break;
         // input gradient of this layer -> pre-activation gradient of the layer below
         GemmArgs d{};

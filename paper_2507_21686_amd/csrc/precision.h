@@ -29,6 +29,8 @@
 #include <float.h>
 #include <math.h>
 
+#include "fastmath.h"
+
 namespace sphbi {
 
 struct ExactMath {
@@ -43,16 +45,16 @@ struct ExactMath {
     template <typename S>
     __host__ __device__ void sector_seed(const S &p, const S &ay, const S &yc, S &ir, S &ang) const {
         ir = 1.0 / sqrt(p * p + ay * ay);
-        ang = atan2(p * (ay - yc), p * p + ay * yc);
+        ang = atan2_q1(p * (ay - yc), p * p + ay * yc);     // both arguments >= 0, the second > 0
     }
     // H_0 = asinh(yB/p) - asinh(yA/p) from f = (|y| + rho)/p at both ends
     template <typename S>
     __host__ __device__ S h0(const S &p, const S &yA, const S &yB, const S &rA, const S &rB) const {
         const S ip = 1.0 / p;
         const S fA = (fabs(yA) + rA) * ip, fB = (fabs(yB) + rB) * ip;
-        if ((yA < 0.0 && yB > 0.0) || (yA > 0.0 && yB < 0.0)) return (yB > 0.0 ? 1.0 : -1.0) * log(fA * fB);
-        if (yB != 0.0) return (yB > 0.0 ? 1.0 : -1.0) * log(fB / fA);
-        return (yA > 0.0 ? -1.0 : 1.0) * log(fA);
+        if ((yA < 0.0 && yB > 0.0) || (yA > 0.0 && yB < 0.0)) return (yB > 0.0 ? 1.0 : -1.0) * log_pos(fA * fB);
+        if (yB != 0.0) return (yB > 0.0 ? 1.0 : -1.0) * log_pos(fB / fA);
+        return (yA > 0.0 ? -1.0 : 1.0) * log_pos(fA);
     }
     // length and inverse length of an edge vector
     template <typename S>
@@ -98,7 +100,7 @@ struct MixedMath {
         }
         if (fp64_angles) {
             ir = rsqrt_(p * p + ay * ay);
-            ang = atan2(p * (ay - yc), p * p + ay * yc);
+            ang = atan2_q1(p * (ay - yc), p * p + ay * yc);
             return;
         }
         ir = rsq_f32((float)(p * p + ay * ay));
@@ -118,7 +120,7 @@ struct MixedMath {
             arg = gA * rcp_(p);
             sg = yA > 0.0 ? -1.0 : 1.0;
         }
-        return sg * log(arg);
+        return sg * log_pos(arg);
     }
     __device__ void edge_norm(double len2, double &len, double &il) const {
         il = rsqrt_(len2);
