@@ -2,14 +2,26 @@
 // particle, gradients with respect to particle positions, triangle vertices
 // and nodal field values.
 //
-// Nothing from the forward pass is stored: every pair recomputes its field
-// record and its clipping/decomposition.  Derivatives with respect to the six
-// vertex coordinates come from a forward-mode dual-number evaluation of the
-// same closed forms (pairmath.h), including the dependence of the field
-// polynomial on the vertices.  The particle gradient follows from
-// translation invariance (moving particle and triangle together changes
-// nothing): d/dx = -(d/dv0 + d/dv1 + d/dv2).  The integrals are linear in
-// the nodal values, so d/dA_n is the pair evaluated with the unit field e_n.
+// With the cotangent-weighted kernel Phi(x) = gI W + gGx dW/dx_p + gGy dW/dy_p
+// a pair contributes L = int_T A Phi dx.  Nothing from the forward pass is
+// stored; every pair recomputes its field and clipping.
+//   * Vertices (Reynolds transport, the Leibniz rule for a moving domain):
+//     moving vertex k by e_alpha moves the boundary with velocity
+//     lambda_k e_alpha (lambda_k its barycentric hat) and, the nodes moving
+//     with the triangle, changes the field at a fixed point by
+//     -lambda_k dA/dx_alpha, so
+//       dL/dv_k,alpha = oint_dT A Phi lambda_k n_alpha ds
+//                       + int_T (-lambda_k dA/dx_alpha) Phi dx.
+//     Along an edge the boundary integral is a polynomial in the edge
+//     coordinate times the kernel and its derivative, which reduce to the
+//     radial terms H_c = int rho^(c-1) dy and powers of rho used by the forward
+//     pass (edge_line below).
+//   * Nodal values and the field part of the vertex term are linear in the
+//     field: both follow from the moments m_j = int_T xi^j Phi dx of the
+//     monomials about the particle (one closed-form evaluation per monomial,
+//     pair_core).
+//   * The particle gradient follows from translation invariance:
+//     d/dx = -(d/dv0 + d/dv1 + d/dv2).
 //
 // Particle gradients are summed per particle with the forward kernel's
 // segmented wave scan.  Per-pair triangle gradients go to a buffer and are
@@ -20,14 +32,155 @@
 
 #include <hipcub/hipcub.hpp>
 
-#include "dual.h"
 #include "internal.h"
 #include "pairmath.h"
 
 namespace sphbi {
 namespace {
 
-using D6 = Dual<6>;
+// Boundary term of one edge: with the particle at the origin (units of h), the
+// edge on the line p n + y tau (tau = (-ny, nx)) from y = ya (vertex a) to
+// y = yb (vertex b) and the field A given about the particle by c,
+//   Ja = int (1 - t) A Phi ds,   Jb = int t A Phi ds   (t = (y - ya)/(yb - ya)),
+// over the parts of the edge inside each kernel piece, in world units.
+template <int DEG, int ORDER>
+__device__ inline void edge_line(const KArgs &K, double p, double ya, double yb, double nx, double ny,
+                                 const double *__restrict__ c, double gI, double gX, double gY, double invh,
+                                 double &Ja, double &Jb) {
+    constexpr int NP = ORDER + 2;                 // t A has degree ORDER + 1
+    constexpr int NQ = ORDER + 3;                 // t A (p gn + y gt) has degree ORDER + 2
+    constexpr int HL = DEG + ORDER + 3;
+    Ja = Jb = 0.0;
+    // A along the line: xi_x = p nx - y ny, xi_y = p ny + y nx
+    double X[4][4], Y[4][4];                      // coefficients of X^i, Y^j in y
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) X[i][q] = Y[i][q] = 0.0;
+    X[0][0] = Y[0][0] = 1.0;
+#pragma unroll
+    for (int i = 1; i <= ORDER; ++i)
+#pragma unroll
+        for (int q = 0; q <= i; ++q) {
+            X[i][q] = p * nx * X[i - 1][q] + (q > 0 ? -ny * X[i - 1][q - 1] : 0.0);
+            Y[i][q] = p * ny * Y[i - 1][q] + (q > 0 ? nx * Y[i - 1][q - 1] : 0.0);
+        }
+    double Ay[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m <= ORDER; ++m)
+#pragma unroll
+        for (int j = 0; j <= m; ++j) {
+            const int i = m - j;
+            const double cij = c[pidx(i, j)];
+#pragma unroll
+            for (int qa = 0; qa <= i; ++qa)
+#pragma unroll
+                for (int qb = 0; qb <= j; ++qb) Ay[qa + qb] += cij * X[i][qa] * Y[j][qb];
+        }
+    // Pb = t A, Pa = A - Pb
+    const double il = 1.0 / (yb - ya);
+    double Pa[NP], Pb[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const double prev = q > 0 ? Ay[q - 1] : 0.0;
+        const double cur = q <= ORDER ? Ay[q] : 0.0;
+        Pb[q] = il * (prev - ya * cur);
+        Pa[q] = cur - Pb[q];
+    }
+    // gX xi_x + gY xi_y = p gn + y gt
+    const double gn = gX * nx + gY * ny, gt = -gX * ny + gY * nx;
+    double Qa[NQ], Qb[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        Qa[q] = (q < NP ? p * gn * Pa[q] : 0.0) + (q > 0 ? gt * Pa[q - 1] : 0.0);
+        Qb[q] = (q < NP ? p * gn * Pb[q] : 0.0) + (q > 0 ? gt * Pb[q - 1] : 0.0);
+    }
+    const double lo0 = fmin(ya, yb), hi0 = fmax(ya, yb);
+    const double p2 = p * p;
+    for (int pc = 0; pc < K.npieces; ++pc) {
+        const double R = K.R[pc];
+        if (!(p < R)) continue;
+        const double yc = sqrt((R - p) * (R + p));
+        const double lo = fmax(lo0, -yc), hi = fmin(hi0, yc);
+        if (!(lo < hi)) continue;
+        const double rl = sqrt(p2 + lo * lo), rh = sqrt(p2 + hi * hi);
+        // H_c = int_lo^hi rho^(c-1) dy; H_0 = asinh(hi/p) - asinh(lo/p), only
+        // ever multiplied by p or p^2, so 0 on a line through the particle
+        double H[HL + 1];
+        if (p > 0.0) {
+            const double fl = fabs(lo) + rl, fh = fabs(hi) + rh;
+            // asinh(y/p) = sign(y) log((|y| + rho)/p)
+            if (lo < 0.0 && hi > 0.0) H[0] = log(fl * fh / p2);
+            else if (hi > 0.0) H[0] = log(fh / fl);
+            else H[0] = log(fl / fh);
+        } else {
+            H[0] = 0.0;
+        }
+        H[1] = hi - lo;
+        double gl = 1.0, gh = 1.0;
+#pragma unroll
+        for (int k = 2; k <= HL; ++k) {
+            gl *= rl;
+            gh *= rh;
+            H[k] = (gh * hi - gl * lo + (k - 1) * p2 * H[k - 2]) * (1.0 / k);
+        }
+        // E_e = int_lo^hi y rho^(e-2) dy = (rh^e - rl^e) / e
+        double E[HL + 1];
+        E[0] = 0.0;
+        double el = 1.0, eh = 1.0;
+#pragma unroll
+        for (int e = 1; e <= HL; ++e) {
+            el *= rl;
+            eh *= rh;
+            E[e] = (eh - el) * (1.0 / e);
+        }
+        // Y(a, cc) = int y^a rho^cc dy, by y^2 = rho^2 - p^2:
+        //   a = 2m:     sum_i C(m,i) (-p^2)^(m-i) H_{2i+cc+1}
+        //   a = 2m+1:   sum_i C(m,i) (-p^2)^(m-i) E_{2i+cc+2}
+        // (a <= 5, so m <= 2 and C(2,1) = 2 is the only coefficient above 1)
+        auto Yac = [&](int a, int cc) -> double {
+            const int m = a >> 1;
+            double s = 0.0, pw = 1.0;
+#pragma unroll
+            for (int i = 2; i >= 0; --i) {
+                if (i > m) continue;
+                const double w = (m == 2 && i == 1 ? 2.0 : 1.0) * pw;
+                s += w * ((a & 1) ? E[2 * i + cc + 2] : H[2 * i + cc + 1]);
+                pw *= -p2;
+            }
+            return s;
+        };
+        double s1a = 0.0, s1b = 0.0, s2a = 0.0, s2b = 0.0;
+#pragma unroll
+        for (int j = 0; j <= DEG; ++j) {
+            const double bj = K.b[pc][j];
+            if (bj == 0.0) continue;
+            double ya1 = 0.0, yb1 = 0.0;
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                const double y = Yac(a, j);
+                ya1 += Pa[a] * y;
+                yb1 += Pb[a] * y;
+            }
+            s1a += bj * ya1;
+            s1b += bj * yb1;
+            if (j >= 1) {
+                double ya2 = 0.0, yb2 = 0.0;
+#pragma unroll
+                for (int a = 0; a < NQ; ++a) {
+                    const double y = Yac(a, j - 2);
+                    ya2 += Qa[a] * y;
+                    yb2 += Qb[a] * y;
+                }
+                s2a += j * bj * ya2;
+                s2b += j * bj * yb2;
+            }
+        }
+        const double f = K.cd * invh;
+        Ja += f * (gI * s1a - invh * s2a);
+        Jb += f * (gI * s1b - invh * s2b);
+    }
+}
 
 template <int DEG, int ORDER>
 __global__ __launch_bounds__(256) void adjoint_kernel(const KArgs K, double invh, int64_t N,
@@ -40,6 +193,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const KArgs K, double invh
                                                       const double *__restrict__ gY, double *__restrict__ dpx,
                                                       double *__restrict__ dpy, double *__restrict__ pair_grad) {
     constexpr int NN = ORDER == 0 ? 1 : (ORDER == 1 ? 3 : 10);
+    constexpr int NM = NN;                        // monomials of degree <= ORDER
     constexpr int NG = 6 + NN;
     const int lane = threadIdx.x & 63;
     const int64_t p0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
@@ -76,32 +230,113 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const KArgs K, double invh
                 for (int k = 0; k < 6; ++k) v[k] = tri[k * T + t];
 #pragma unroll
                 for (int k = 0; k < 10; ++k) A[k] = k < NN ? nodal[k * T + t] : 0.0;
-                // vertices: six dual directions
-                {
-                    D6 vd[6], Ad[10], rec[kRecDoubles];
+                double ax[3], ay[3];
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) {
-                        vd[k] = D6(v[k]);
-                        vd[k].d[k] = 1.0;
-                    }
-#pragma unroll
-                    for (int k = 0; k < 10; ++k) Ad[k] = D6(A[k]);
-                    prepare_record<ORDER, D6>(vd, Ad, invh, rec);
-                    D6 oI, oX, oY;
-                    pair_fwd<DEG, ORDER, D6>(K, ExactMath(), 0.0, D6(x), D6(y), invh, rec, oI, oX, oY);
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) grad[k] = cI * oI.d[k] + cX * oX.d[k] + cY * oY.d[k];
+                for (int i = 0; i < 3; ++i) {
+                    ax[i] = (v[2 * i] - x) * invh;
+                    ay[i] = (v[2 * i + 1] - y) * invh;
                 }
-                // nodal values: the integrals are linear in them
+                const double area2 = (ax[1] - ax[0]) * (ay[2] - ay[0]) - (ax[2] - ax[0]) * (ay[1] - ay[0]);
+                if (area2 != 0.0) {
+                    // field about the particle
+                    double rec[kRecDoubles], c[10];
+                    prepare_record<ORDER, double>(v, A, invh, rec);
+                    taylor_shift<ORDER, double>(rec + 6, ax[0], ay[0], c);
+                    // moments of the monomials about the particle
+                    double mom[NM];
 #pragma unroll 1
-                for (int n = 0; n < NN; ++n) {
-                    double Au[10], rec[kRecDoubles];
+                    for (int j = 0; j < NM; ++j) {
+                        double cu[10];
 #pragma unroll
-                    for (int k = 0; k < 10; ++k) Au[k] = k == n ? 1.0 : 0.0;
-                    prepare_record<ORDER, double>(v, Au, invh, rec);
-                    double oI, oX, oY;
-                    pair_fwd<DEG, ORDER, double>(K, ExactMath(), 0.0, x, y, invh, rec, oI, oX, oY);
-                    grad[6 + n] = cI * oI + cX * oX + cY * oY;
+                        for (int k = 0; k < 10; ++k) cu[k] = k == j ? 1.0 : 0.0;
+                        double oI, oX, oY;
+                        pair_core<DEG, ORDER, double>(K, ExactMath(), 0.0, ax, ay, area2, cu, invh, oI, oX, oY);
+                        const double mj = cI * oI + cX * oX + cY * oY;
+#pragma unroll
+                        for (int k = 0; k < NM; ++k)
+                            if (k == j) mom[k] = mj;
+                    }
+                    // nodal values: the Lagrange basis functions about the particle
+#pragma unroll 1
+                    for (int n = 0; n < NN; ++n) {
+                        double Au[10], rn[kRecDoubles], cn[10];
+#pragma unroll
+                        for (int k = 0; k < 10; ++k) Au[k] = k == n ? 1.0 : 0.0;
+                        prepare_record<ORDER, double>(v, Au, invh, rn);
+                        taylor_shift<ORDER, double>(rn + 6, ax[0], ay[0], cn);
+                        double s = 0.0;
+#pragma unroll
+                        for (int k = 0; k < NM; ++k) s += cn[k] * mom[k];
+#pragma unroll
+                        for (int k = 0; k < NN; ++k)
+                            if (k == n) grad[6 + k] = s;
+                    }
+                    // vertices, field part: -lambda_k dA/dx_alpha (ORDER >= 1)
+                    if (ORDER >= 1) {
+                        const double q1x = ax[1] - ax[0], q1y = ay[1] - ay[0];
+                        const double q2x = ax[2] - ax[0], q2y = ay[2] - ay[0];
+                        const double id = 1.0 / area2;
+                        const double l1x = q2y * id, l1y = -q2x * id, l2x = -q1y * id, l2y = q1x * id;
+                        const double lx[3] = {-(l1x + l2x), l1x, l2x};
+                        const double ly[3] = {-(l1y + l2y), l1y, l2y};
+                        // gradient of A in xi (units of h)
+                        double dxA[10], dyA[10];
+#pragma unroll
+                        for (int k = 0; k < 10; ++k) dxA[k] = dyA[k] = 0.0;
+#pragma unroll
+                        for (int m = 1; m <= ORDER; ++m)
+#pragma unroll
+                            for (int j = 0; j <= m; ++j) {
+                                const int i = m - j;
+                                if (i > 0) dxA[pidx(i - 1, j)] += i * c[pidx(i, j)];
+                                if (j > 0) dyA[pidx(i, j - 1)] += j * c[pidx(i, j)];
+                            }
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            // lambda_k about the particle: 1 at vertex k, 0 at the others
+                            const double l0 = (k == 0 ? 1.0 : 0.0) - lx[k] * ax[0] - ly[k] * ay[0];
+                            double bx[10], by[10];
+                            mul_affine<double>(dxA, l0, lx[k], ly[k], bx);
+                            mul_affine<double>(dyA, l0, lx[k], ly[k], by);
+                            double sx = 0.0, sy = 0.0;
+#pragma unroll
+                            for (int j = 0; j < NM; ++j) {
+                                sx += bx[j] * mom[j];
+                                sy += by[j] * mom[j];
+                            }
+                            grad[2 * k] -= invh * sx;
+                            grad[2 * k + 1] -= invh * sy;
+                        }
+                    }
+                    // vertices, boundary part
+                    const double so = area2 > 0.0 ? 1.0 : -1.0;
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+                        const int f = e == 2 ? 0 : e + 1;
+                        const double Lx = ax[f] - ax[e], Ly = ay[f] - ay[e];
+                        const double len2 = Lx * Lx + Ly * Ly;
+                        if (len2 == 0.0) continue;
+                        const double len = sqrt(len2), ilen = 1.0 / len;
+                        const double tx = Lx * ilen, ty = Ly * ilen;
+                        const double sd = ax[e] * ty - ay[e] * tx;
+                        const double pe = fabs(sd);
+                        const double nx = sd > 0.0 ? ty : -ty, ny = sd > 0.0 ? -tx : tx;
+                        const double ya = -ax[e] * ny + ay[e] * nx, yb = -ax[f] * ny + ay[f] * nx;
+                        double Je, Jf;
+                        edge_line<DEG, ORDER>(K, pe, ya, yb, nx, ny, c, cI, cX, cY, invh, Je, Jf);
+                        const double ox = so * ty, oy = -so * tx;      // outward unit normal
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            if (k == e) {
+                                grad[2 * k] += Je * ox;
+                                grad[2 * k + 1] += Je * oy;
+                            }
+                            if (k == f) {
+                                grad[2 * k] += Jf * ox;
+                                grad[2 * k + 1] += Jf * oy;
+                            }
+                        }
+                    }
                 }
             }
             vx = -(grad[0] + grad[2] + grad[4]);

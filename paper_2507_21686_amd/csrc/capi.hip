@@ -133,6 +133,7 @@ KArgs make_kargs(const sphbi_kernel *k, int *deg_out) {
             double sv = 0.0, sw = 0.0;
             for (int j = 0; j <= k->degree[p]; ++j) {
                 const double b = k->b[p][j];
+                K.b[p][j] = b;
                 K.bq[p][m][j] = b / (j + 2 + m);
                 K.kbq[p][m][j] = j * b / (j + 1 + m);
                 sv += b * pow(R, j + 2 + m) / (j + 2 + m);

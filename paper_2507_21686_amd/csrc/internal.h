@@ -13,6 +13,7 @@ constexpr int kMaxDeg = 11;     // kernel polynomial degree
 
 // Device-side kernel description, derived on the host from sphbi_kernel.
 // R[p], iR[p]  = piece radius and its inverse (units of h)
+// b[p][k]      = kernel coefficients of the piece
 // bq[p][m][k]  = b_k / (k + 2 + m)     (value, field degree m)
 // kbq[p][m][k] = k b_k / (k + 1 + m)   (gradient, field degree m)
 // sv[p][m]     = sum_k b_k R^{k+2+m} / (k+2+m)   (value of a unit sector)
@@ -22,6 +23,7 @@ struct KArgs {
     int pad;
     double R[2];
     double iR[2];
+    double b[2][kMaxDeg + 1];
     double bq[2][kMaxOrder + 1][kMaxDeg + 1];
     double kbq[2][kMaxOrder + 1][kMaxDeg + 1];
     double sv[2][kMaxOrder + 1];

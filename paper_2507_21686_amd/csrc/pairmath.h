@@ -353,6 +353,11 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
 // tau: edges whose line passes within tau (units of h) of the particle are
 // evaluated with the exact policy (only meaningful for MixedMath).
 template <int DEG, int ORDER, typename S, typename M>
+__host__ __device__ inline void pair_core(const KArgs &K, const M &math, double tau, const S *ax, const S *ay,
+                                          const S &area2, const S *c, double invh, S &oI, S &oX, S &oY);
+
+// One pair: particle (x, y), record r (vertices and field about vertex 0).
+template <int DEG, int ORDER, typename S, typename M>
 __host__ __device__ inline void pair_fwd(const KArgs &K, const M &math, double tau, S x, S y, double invh,
                                          const S *__restrict__ r, S &oI, S &oX, S &oY) {
     oI = oX = oY = 0.0;
@@ -366,6 +371,15 @@ __host__ __device__ inline void pair_fwd(const KArgs &K, const M &math, double t
     if (area2 == 0.0) return;
     S c[10];
     taylor_shift<ORDER, S>(r + 6, ax[0], ay[0], c);
+    pair_core<DEG, ORDER, S, M>(K, math, tau, ax, ay, area2, c, invh, oI, oX, oY);
+}
+
+// The pair for a field given as a polynomial about the particle:
+// A(x + h xi) = sum c_ij xi_x^i xi_y^j, vertices (ax, ay) in units of h
+// relative to the particle, area2 their doubled signed area (non-zero).
+template <int DEG, int ORDER, typename S, typename M>
+__host__ __device__ inline void pair_core(const KArgs &K, const M &math, double tau, const S *ax, const S *ay,
+                                          const S &area2, const S *c, double invh, S &oI, S &oX, S &oY) {
     Harm<S> hg[ORDER + 1];
     global_harmonics<ORDER, S>(c, hg);
     S I = 0.0, GX = 0.0, GY = 0.0;
