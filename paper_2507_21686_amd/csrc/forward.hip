@@ -69,8 +69,20 @@ __global__ __launch_bounds__(256) void prepare_kernel(int64_t T, const double *_
     for (int k = 0; k < kRecDoubles; ++k) o[k] = r[k];
 }
 
+// Waves per SIMD that each instantiation is compiled for (the register
+// budget is 512 / waves).  A single wavefront issues an FP64 operation only
+// every 5-7 cycles even with independent work (measured on gfx950), so a
+// second or third resident wave raises the issue rate as long as the register
+// cut costs little spilling.  The table is the fastest of 1, 2 and 3 waves
+// per instantiation on the covering workload; the cubic-field variant of the
+// degree-11 kernel spills too much at two waves and stays at one.
+__host__ __device__ constexpr int fwd_waves(int deg, int order, bool mixed) {
+    return order >= 2 ? (deg <= 8 ? 2 : 1) : order == 1 ? (mixed && deg <= 5 ? 3 : 2) : 3;
+}
+__host__ __device__ constexpr int fwd_edge_unroll(int deg, int order) { return order >= 2 && deg > 8 ? 1 : 3; }
+
 template <int DEG, int ORDER, bool MIXED>
-__global__ __launch_bounds__(256) void forward_kernel(const KArgs K, double tau, double invh, int64_t N,
+__global__ __launch_bounds__(256, fwd_waves(DEG, ORDER, MIXED)) void forward_kernel(const KArgs K, double tau, double invh, int64_t N,
                                                       const double *__restrict__ px,
                                                       const double *__restrict__ py,
                                                       const int64_t *__restrict__ off,
@@ -106,10 +118,12 @@ __global__ __launch_bounds__(256) void forward_kernel(const KArgs K, double tau,
             const int32_t t = tri_idx[q];
             if (t >= 0 && t < T) {   // out-of-range triangle indices contribute nothing
                 const double *r = rec + (int64_t)t * kRecDoubles;
+                constexpr int EU = fwd_edge_unroll(DEG, ORDER);
                 if (MIXED)
-                    pair_fwd<DEG, ORDER, double>(K, MixedMath{false, ORDER >= 2}, tau, px[ip], py[ip], invh, r, vI,
-                                                 vX, vY);
-                else pair_fwd<DEG, ORDER, double>(K, ExactMath(), 0.0, px[ip], py[ip], invh, r, vI, vX, vY);
+                    pair_fwd<DEG, ORDER, double, MixedMath, EU>(K, MixedMath{false, ORDER >= 2}, tau, px[ip], py[ip],
+                                                                invh, r, vI, vX, vY);
+                else pair_fwd<DEG, ORDER, double, ExactMath, EU>(K, ExactMath(), 0.0, px[ip], py[ip], invh, r, vI, vX,
+                                                                 vY);
             }
             if (per_pair) {
                 per_pair[q] = vI;

@@ -242,11 +242,29 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
             dn1 = dn; tn1 = tn; dn = dn2; tn = tn2;
         }
     }
+    // contract the sector parts now, so that the angular terms are dead
+    // before the radial terms are formed
+    if (clipA || clipB) {
+#pragma unroll
+        for (int m = 0; m <= ORDER; ++m) {
+            Harm<S> hx, hy;
+            mul_cs(m, hv[m], hx, hy);
+            const double sv = K.sv[pc][m], sw = K.sw[pc][m];
+#pragma unroll
+            for (int n = m & 1; n <= m; n += 2) oI += sv * (hv[m].c[n] * angc[n] + hv[m].s[n] * angs[n]);
+#pragma unroll
+            for (int n = (m + 1) & 1; n <= m + 1; n += 2) {
+                oX += sw * (hx.c[n] * angc[n] + hx.s[n] * angs[n]);
+                oY += sw * (hy.c[n] * angc[n] + hy.s[n] * angs[n]);
+            }
+        }
+    }
 
     // ---- triangle parts: radial 2F1 terms H_c and powers P_e
-    S H[HMAX + 1], P[PMAX + 1];
     const bool tri = p < R && (aya > 0.0 || ayb > 0.0);
-    if (tri) {
+    if (!tri) return;
+    S H[HMAX + 1], P[PMAX + 1];
+    {
         const S yA = clipA ? S(copysign(yc, ya)) : ya;
         const S yB = clipB ? S(copysign(yc, yb)) : yb;
         const S rA = clipA ? S(R) : S(math.sqrt_(p * p + ya * ya));
@@ -280,18 +298,6 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
     for (int m = 0; m <= ORDER; ++m) {
         Harm<S> hx, hy;
         mul_cs(m, hv[m], hx, hy);
-        // sector parts
-        const double sv = K.sv[pc][m], sw = K.sw[pc][m];
-        if (clipA || clipB) {
-#pragma unroll
-            for (int n = m & 1; n <= m; n += 2) oI += sv * (hv[m].c[n] * angc[n] + hv[m].s[n] * angs[n]);
-#pragma unroll
-            for (int n = (m + 1) & 1; n <= m + 1; n += 2) {
-                oX += sw * (hx.c[n] * angc[n] + hx.s[n] * angs[n]);
-                oY += sw * (hy.c[n] * angc[n] + hy.s[n] * angs[n]);
-            }
-        }
-        if (!tri) continue;
         // kernel-contracted radial sums
         S Ac[ORDER + 1], As[ORDER + 1], Bc[ORDER + 2], Bs[ORDER + 1];
 #pragma unroll
@@ -352,12 +358,12 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
 
 // tau: edges whose line passes within tau (units of h) of the particle are
 // evaluated with the exact policy (only meaningful for MixedMath).
-template <int DEG, int ORDER, typename S, typename M>
+template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL = 3>
 __host__ __device__ inline void pair_core(const KArgs &K, const M &math, double tau, const S *ax, const S *ay,
                                           const S &area2, const S *c, double invh, S &oI, S &oX, S &oY);
 
 // One pair: particle (x, y), record r (vertices and field about vertex 0).
-template <int DEG, int ORDER, typename S, typename M>
+template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL = 3>
 __host__ __device__ inline void pair_fwd(const KArgs &K, const M &math, double tau, S x, S y, double invh,
                                          const S *__restrict__ r, S &oI, S &oX, S &oY) {
     oI = oX = oY = 0.0;
@@ -371,23 +377,30 @@ __host__ __device__ inline void pair_fwd(const KArgs &K, const M &math, double t
     if (area2 == 0.0) return;
     S c[10];
     taylor_shift<ORDER, S>(r + 6, ax[0], ay[0], c);
-    pair_core<DEG, ORDER, S, M>(K, math, tau, ax, ay, area2, c, invh, oI, oX, oY);
+    pair_core<DEG, ORDER, S, M, EDGE_UNROLL>(K, math, tau, ax, ay, area2, c, invh, oI, oX, oY);
 }
 
 // The pair for a field given as a polynomial about the particle:
 // A(x + h xi) = sum c_ij xi_x^i xi_y^j, vertices (ax, ay) in units of h
 // relative to the particle, area2 their doubled signed area (non-zero).
-template <int DEG, int ORDER, typename S, typename M>
+// EDGE_UNROLL = 1 keeps the edge loop rolled (one edge's state live at a
+// time), 3 unrolls it.
+template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL>
 __host__ __device__ inline void pair_core(const KArgs &K, const M &math, double tau, const S *ax, const S *ay,
                                           const S &area2, const S *c, double invh, S &oI, S &oX, S &oY) {
     Harm<S> hg[ORDER + 1];
     global_harmonics<ORDER, S>(c, hg);
     S I = 0.0, GX = 0.0, GY = 0.0;
-#pragma unroll
+    // the vertex registers rotate, so that the loop body is the same for every edge
+    S x0 = ax[0], y0 = ay[0], x1 = ax[1], y1 = ay[1], x2 = ax[2], y2 = ay[2];
+#pragma unroll EDGE_UNROLL
     for (int e = 0; e < 3; ++e) {
-        const int f = e == 2 ? 0 : e + 1;
-        const S axe = ax[e], aye = ay[e];
-        const S Lx = ax[f] - axe, Ly = ay[f] - aye;
+        const S axe = x0, aye = y0;
+        const S Lx = x1 - axe, Ly = y1 - aye;
+        {
+            const S rx = x0, ry = y0;
+            x0 = x1; y0 = y1; x1 = x2; y1 = y2; x2 = rx; y2 = ry;
+        }
         const S len2 = Lx * Lx + Ly * Ly;
         if (len2 == 0.0) continue;
         S len, il;

@@ -47,14 +47,27 @@ struct ExactMath {
         ir = 1.0 / sqrt(p * p + ay * ay);
         ang = atan2_q1(p * (ay - yc), p * p + ay * yc);     // both arguments >= 0, the second > 0
     }
-    // H_0 = asinh(yB/p) - asinh(yA/p) from f = (|y| + rho)/p at both ends
+    // H_0 = asinh(yB/p) - asinh(yA/p), with asinh(|y|/p) = log((|y| + rho)/p):
+    // one quotient and one logarithm whichever signs the ends have
     template <typename S>
     __host__ __device__ S h0(const S &p, const S &yA, const S &yB, const S &rA, const S &rB) const {
-        const S ip = 1.0 / p;
-        const S fA = (fabs(yA) + rA) * ip, fB = (fabs(yB) + rB) * ip;
-        if ((yA < 0.0 && yB > 0.0) || (yA > 0.0 && yB < 0.0)) return (yB > 0.0 ? 1.0 : -1.0) * log_pos(fA * fB);
-        if (yB != 0.0) return (yB > 0.0 ? 1.0 : -1.0) * log_pos(fB / fA);
-        return (yA > 0.0 ? -1.0 : 1.0) * log_pos(fA);
+        const S gA = fabs(yA) + rA, gB = fabs(yB) + rB;
+        S num, den;
+        double sg;
+        if ((yA < 0.0 && yB > 0.0) || (yA > 0.0 && yB < 0.0)) {
+            num = gA * gB;
+            den = p * p;
+            sg = yB > 0.0 ? 1.0 : -1.0;
+        } else if (yB != 0.0) {
+            num = gB;
+            den = gA;
+            sg = yB > 0.0 ? 1.0 : -1.0;
+        } else {
+            num = gA;
+            den = p;
+            sg = yA > 0.0 ? -1.0 : 1.0;
+        }
+        return sg * log_pos(num / den);
     }
     // length and inverse length of an edge vector
     template <typename S>
@@ -109,18 +122,21 @@ struct MixedMath {
     __device__ double h0(double p, double yA, double yB, double rA, double rB) const {
         if (exact) return ExactMath().h0(p, yA, yB, rA, rB);
         const double gA = fabs(yA) + rA, gB = fabs(yB) + rB;
-        double arg, sg;
+        double num, den, sg;
         if ((yA < 0.0 && yB > 0.0) || (yA > 0.0 && yB < 0.0)) {
-            arg = gA * gB * rcp_(p * p);
+            num = gA * gB;
+            den = p * p;
             sg = yB > 0.0 ? 1.0 : -1.0;
         } else if (yB != 0.0) {
-            arg = gB * rcp_(gA);
+            num = gB;
+            den = gA;
             sg = yB > 0.0 ? 1.0 : -1.0;
         } else {
-            arg = gA * rcp_(p);
+            num = gA;
+            den = p;
             sg = yA > 0.0 ? -1.0 : 1.0;
         }
-        return sg * log_pos(arg);
+        return sg * log_pos(num * rcp_(den));
     }
     __device__ void edge_norm(double len2, double &len, double &il) const {
         il = rsqrt_(len2);
