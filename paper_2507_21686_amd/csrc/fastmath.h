@@ -11,54 +11,66 @@
 
 namespace sphbi {
 
+// An FP64 constant cannot be an instruction literal on this target.  Written
+// inline, each coefficient would be materialised once in a vector register
+// pair and kept for the whole loop it is hoisted out of; under register
+// pressure the compiler then spills it and reloads it from scratch memory
+// inside the polynomial.  sconst() hands the constant over through an opaque
+// scalar-register operand at the point of use, so it costs two scalar moves
+// (issued beside the vector work) and no vector register.
+__device__ inline double sconst(double c) {
+    asm volatile("" : "+s"(c));
+    return c;
+}
+
 // atan(y / x) for y >= 0, x > 0.  After swapping so that the ratio is at
 // most 1, the identity atan(t) = pi/4 + atan((t - 1)/(t + 1)) brings it to
-// |u| <= tan(pi/8) with one division, where atan(u) = u P(u^2) (degree 10,
-// relative error 7e-17).
-__host__ __device__ inline double atan2_q1(double y, double x) {
+// |u| <= tan(pi/8) with one division, where atan(u) = u + u^3 P(u^2)
+// (P of degree 9, relative error 7e-17).
+__device__ inline double atan2_q1(double y, double x) {
     const bool swap = y > x;
     const double num = swap ? x : y, den = swap ? y : x;
-    const bool big = num > 0.41421356237309503 * den;
+    const bool big = num > sconst(0.41421356237309503) * den;
     const double u = (big ? num - den : num) / (big ? num + den : den);
     const double s = u * u;
-    double p = 0.02114282795405936;
-    p = fma(p, s, -0.043486934438068184);
-    p = fma(p, s, 0.05688583712710041);
-    p = fma(p, s, -0.06640281421077107);
-    p = fma(p, s, 0.07689959311291694);
-    p = fma(p, s, -0.09090773515721326);
-    p = fma(p, s, 0.11111106200822037);
-    p = fma(p, s, -0.1428571418151725);
-    p = fma(p, s, 0.1999999999886241);
-    p = fma(p, s, -0.33333333333328474);
+    double p = sconst(0.02114282795405936);
+    p = fma(p, s, sconst(-0.043486934438068184));
+    p = fma(p, s, sconst(0.05688583712710041));
+    p = fma(p, s, sconst(-0.06640281421077107));
+    p = fma(p, s, sconst(0.07689959311291694));
+    p = fma(p, s, sconst(-0.09090773515721326));
+    p = fma(p, s, sconst(0.11111106200822037));
+    p = fma(p, s, sconst(-0.1428571418151725));
+    p = fma(p, s, sconst(0.1999999999886241));
+    p = fma(p, s, sconst(-0.33333333333328474));
     double a = fma(u * s, p, u);
-    if (big) a += 0.7853981633974483;
-    return swap ? 1.5707963267948966 - a : a;
+    if (big) a += sconst(0.7853981633974483);
+    return swap ? sconst(1.5707963267948966) - a : a;
 }
 
 // log(x) for finite normal x > 0: x = m 2^e with m in [1/sqrt 2, sqrt 2),
-// log m = 2 atanh(s) = s Q(s^2), s = (m - 1)/(m + 1) (degree 8, relative
-// error 7e-19), and e ln 2 with ln 2 split so that e ln2_hi is exact.
-__host__ __device__ inline double log_pos(double x) {
+// log m = 2 atanh(s) = 2 s + s^3 Q(s^2), s = (m - 1)/(m + 1) (Q of degree 7,
+// relative error 7e-19), and e ln 2 with ln 2 split so that e ln2_hi is exact.
+__device__ inline double log_pos(double x) {
     int e;
     double m = frexp(x, &e);                       // m in [1/2, 1)
-    if (m < 0.7071067811865476) {
+    if (m < sconst(0.7071067811865476)) {
         m *= 2.0;
         e -= 1;
     }
     const double s = (m - 1.0) / (m + 1.0);
     const double s2 = s * s;
-    double q = 0.1326226214625569;
-    q = fma(q, s2, 0.13248744435029344);
-    q = fma(q, s2, 0.1538716181755671);
-    q = fma(q, s2, 0.18181773715830785);
-    q = fma(q, s2, 0.22222222677235373);
-    q = fma(q, s2, 0.28571428568816837);
-    q = fma(q, s2, 0.400000000000075);
-    q = fma(q, s2, 0.6666666666666666);
+    double q = sconst(0.1326226214625569);
+    q = fma(q, s2, sconst(0.13248744435029344));
+    q = fma(q, s2, sconst(0.1538716181755671));
+    q = fma(q, s2, sconst(0.18181773715830785));
+    q = fma(q, s2, sconst(0.22222222677235373));
+    q = fma(q, s2, sconst(0.28571428568816837));
+    q = fma(q, s2, sconst(0.400000000000075));
+    q = fma(q, s2, sconst(0.6666666666666666));
     const double lm = fma(s * s2, q, 2.0 * s);
     const double de = (double)e;
-    return fma(de, 0.6931471803691238, fma(de, 1.9082149292705877e-10, lm));
+    return fma(de, sconst(0.6931471803691238), fma(de, sconst(1.9082149292705877e-10), lm));
 }
 
 // generic fallbacks (dual numbers in the adjoint use their own overloads)

@@ -71,13 +71,14 @@ __global__ __launch_bounds__(256) void prepare_kernel(int64_t T, const double *_
 
 // Waves per SIMD that each instantiation is compiled for (the register
 // budget is 512 / waves).  A single wavefront issues an FP64 operation only
-// every 5-7 cycles even with independent work (measured on gfx950), so a
-// second or third resident wave raises the issue rate as long as the register
-// cut costs little spilling.  The table is the fastest of 1, 2 and 3 waves
-// per instantiation on the covering workload; the cubic-field variant of the
-// degree-11 kernel spills too much at two waves and stays at one.
-__host__ __device__ constexpr int fwd_waves(int deg, int order, bool mixed) {
-    return order >= 2 ? (deg <= 8 ? 2 : 1) : order == 1 ? (mixed && deg <= 5 ? 3 : 2) : 3;
+// every 5-7 cycles even with independent work (measured on gfx950), so more
+// resident waves raise the issue rate as long as the register cut costs
+// little spilling.  The table is the fastest of 1-4 waves per instantiation
+// on the covering workload (cubic fields 2, linear 3, constant 4 but 3 for the
+// degree-11 kernel); the cubic-field degree-11 variant keeps its edge loop
+// rolled to fit two waves.
+__host__ __device__ constexpr int fwd_waves(int deg, int order, bool) {
+    return order >= 2 ? 2 : order == 1 ? 3 : (deg <= 8 ? 4 : 3);
 }
 __host__ __device__ constexpr int fwd_edge_unroll(int deg, int order) { return order >= 2 && deg > 8 ? 1 : 3; }
 

@@ -14,6 +14,14 @@ namespace sphbi {
 
 __host__ __device__ constexpr int pidx(int i, int j) { return (i + j) * (i + j + 1) / 2 + j; }
 
+// An FP64 constant as an instruction operand: the values the hardware encodes
+// inline (0, +-1/2, +-1, +-2, +-4) stay literal, every other one is handed
+// over through a scalar register at its point of use (see sconst()).
+__device__ inline double lit(double c) {
+    const double a = fabs(c);
+    return (a == 0.0 || a == 0.5 || a == 1.0 || a == 2.0 || a == 4.0) ? c : sconst(c);
+}
+
 // Chebyshev coefficients: T_n(x) = sum_j chebT(n,j) x^j, U_n likewise.
 __host__ __device__ constexpr double chebT(int n, int j) {
     return n == 0 ? (j == 0 ? 1.0 : 0.0)
@@ -171,10 +179,10 @@ __host__ __device__ inline void global_harmonics(const S *c, Harm<S> *h) {
     }
     if (ORDER >= 3) {
         const S c30 = c[pidx(3, 0)], c21 = c[pidx(2, 1)], c12 = c[pidx(1, 2)], c03 = c[pidx(0, 3)];
-        h[3].c[1] = 0.25 * (3.0 * c30 + c12);
-        h[3].s[1] = 0.25 * (c21 + 3.0 * c03);
-        h[3].c[3] = 0.25 * (c30 - c12);
-        h[3].s[3] = 0.25 * (c21 - c03);
+        h[3].c[1] = lit(0.25) * fma(lit(3.0), c30, c12);
+        h[3].s[1] = lit(0.25) * fma(lit(3.0), c03, c21);
+        h[3].c[3] = lit(0.25) * (c30 - c12);
+        h[3].s[3] = lit(0.25) * (c21 - c03);
     }
 }
 
@@ -196,7 +204,11 @@ __host__ __device__ inline void taylor_shift(const S *__restrict__ e, S sx, S sy
 #pragma unroll
             for (int a = 0; a <= i; ++a)
 #pragma unroll
-                for (int b = 0; b <= j; ++b) c[pidx(a, b)] += eij * B[i][a] * B[j][b] * mx[i - a] * my[j - b];
+                for (int b = 0; b <= j; ++b) {
+                    const double w = B[i][a] * B[j][b];
+                    const S f = w == 1.0 ? eij : S(eij * lit(w));
+                    c[pidx(a, b)] += f * mx[i - a] * my[j - b];
+                }
         }
 }
 
@@ -233,9 +245,10 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
         S dn1 = 1.0, tn1 = 0.0, dn = cpc, tn = spc;    // cos/sin of n psi_c
 #pragma unroll
         for (int n = 1; n <= ORDER + 1; ++n) {
-            const double inv = 1.0 / n;
-            angc[n] += sy * (sn - tn) * inv;
-            angs[n] += sg * (dn - cn) * inv;
+            const double inv = lit(1.0 / n);
+            const double sinv = sy * inv, ginv = sg * inv;
+            angc[n] += (sn - tn) * sinv;
+            angs[n] += (dn - cn) * ginv;
             const S cn2 = 2.0 * cu * cn - cn1, sn2 = 2.0 * cu * sn - sn1;
             const S dn2 = 2.0 * cpc * dn - dn1, tn2 = 2.0 * cpc * tn - tn1;
             cn1 = cn; sn1 = sn; cn = cn2; sn = sn2;
@@ -279,12 +292,12 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
         for (int c = 2; c <= HMAX; ++c) {
             gA *= rA;
             gB *= rB;
-            H[c] = (gB * yB - gA * yA + (c - 1) * p2 * H[c - 2]) * (1.0 / c);
+            H[c] = (gB * yB - gA * yA + lit(c - 1.0) * p2 * H[c - 2]) * lit(1.0 / c);
         }
         S qA = rA, qB = rB;            // rho^{e+1}
 #pragma unroll
         for (int e = 0; e <= PMAX; ++e) {
-            P[e] = (qB - qA) * (1.0 / (e + 1));
+            P[e] = (qB - qA) * lit(1.0 / (e + 1));
             qA *= rA;
             qB *= rB;
         }
@@ -334,10 +347,10 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
             S vc = 0.0, vs = 0.0;
 #pragma unroll
             for (int j = 0; j <= n; ++j)
-                if (chebT(n, j) != 0.0) vc = fma(chebT(n, j) * pj[j], Ac[j], vc);
+                if (chebT(n, j) != 0.0) vc = fma(lit(chebT(n, j)) * pj[j], Ac[j], vc);
 #pragma unroll
             for (int j = 0; j < n; ++j)
-                if (chebU(n - 1, j) != 0.0) vs = fma(chebU(n - 1, j) * pj[j], As[j], vs);
+                if (chebU(n - 1, j) != 0.0) vs = fma(lit(chebU(n - 1, j)) * pj[j], As[j], vs);
             oI += hv[m].c[n] * vc + hv[m].s[n] * vs;
         }
         // gradient harmonics n = m+1, m-1, ...
@@ -346,10 +359,10 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
             S wc = 0.0, ws = 0.0;
 #pragma unroll
             for (int j = 0; j <= n; ++j)
-                if (chebT(n, j) != 0.0) wc = fma(chebT(n, j) * pj[j], Bc[j], wc);
+                if (chebT(n, j) != 0.0) wc = fma(lit(chebT(n, j)) * pj[j], Bc[j], wc);
 #pragma unroll
             for (int j = 0; j < n; ++j)
-                if (chebU(n - 1, j) != 0.0) ws = fma(chebU(n - 1, j) * pj[j], Bs[j], ws);
+                if (chebU(n - 1, j) != 0.0) ws = fma(lit(chebU(n - 1, j)) * pj[j], Bs[j], ws);
             oX += hx.c[n] * wc + hx.s[n] * ws;
             oY += hy.c[n] * wc + hy.s[n] * ws;
         }
