@@ -18,8 +18,10 @@
 //     pass (edge_line below).
 //   * Nodal values and the field part of the vertex term are linear in the
 //     field: both follow from the moments m_j = int_T xi^j Phi dx of the
-//     monomials about the particle (one closed-form evaluation per monomial,
-//     pair_core).
+//     monomials about the particle.  The closed form is linear in the field's
+//     harmonics, so pair_dual gets all of them in one pass; the nodal
+//     gradients are the moments carried back through the shift to the
+//     particle and the field preparation (their transposes).
 //   * The particle gradient follows from translation invariance:
 //     d/dx = -(d/dv0 + d/dv1 + d/dv2).
 //
@@ -242,34 +244,17 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const KArgs K, double invh
                     double rec[kRecDoubles], c[10];
                     prepare_record<ORDER, double>(v, A, invh, rec);
                     taylor_shift<ORDER, double>(rec + 6, ax[0], ay[0], c);
-                    // moments of the monomials about the particle
+                    // moments of the monomials about the particle, in one pass
                     double mom[NM];
-#pragma unroll 1
-                    for (int j = 0; j < NM; ++j) {
-                        double cu[10];
+                    pair_dual<DEG, ORDER>(K, ax, ay, area2, invh, cI, cX, cY, mom);
+                    // nodal values: the moments carried back through the
+                    // shift to the particle and the field preparation
+                    {
+                        double ge[10], gA[10];
+                        taylor_shift_T<ORDER, double>(mom, ax[0], ay[0], ge);
+                        prepare_record_T<ORDER, double>(v, ge, invh, gA);
 #pragma unroll
-                        for (int k = 0; k < 10; ++k) cu[k] = k == j ? 1.0 : 0.0;
-                        double oI, oX, oY;
-                        pair_core<DEG, ORDER, double>(K, ExactMath(), 0.0, ax, ay, area2, cu, invh, oI, oX, oY);
-                        const double mj = cI * oI + cX * oX + cY * oY;
-#pragma unroll
-                        for (int k = 0; k < NM; ++k)
-                            if (k == j) mom[k] = mj;
-                    }
-                    // nodal values: the Lagrange basis functions about the particle
-#pragma unroll 1
-                    for (int n = 0; n < NN; ++n) {
-                        double Au[10], rn[kRecDoubles], cn[10];
-#pragma unroll
-                        for (int k = 0; k < 10; ++k) Au[k] = k == n ? 1.0 : 0.0;
-                        prepare_record<ORDER, double>(v, Au, invh, rn);
-                        taylor_shift<ORDER, double>(rn + 6, ax[0], ay[0], cn);
-                        double s = 0.0;
-#pragma unroll
-                        for (int k = 0; k < NM; ++k) s += cn[k] * mom[k];
-#pragma unroll
-                        for (int k = 0; k < NN; ++k)
-                            if (k == n) grad[6 + k] = s;
+                        for (int n = 0; n < NN; ++n) grad[6 + n] = gA[n];
                     }
                     // vertices, field part: -lambda_k dA/dx_alpha (ORDER >= 1)
                     if (ORDER >= 1) {

@@ -56,6 +56,68 @@ __host__ __device__ inline void mul_affine(const S *in, S a, S bx, S by, S *out)
         }
 }
 
+// Lagrange basis of the element as polynomials in eta = (x - v0)/h: calls
+// fn(node, weight, t) for every node, where weight * t (t ordered like the
+// record's field coefficients) is the node's basis function.  Nothing is
+// called for a degenerate triangle.
+template <int ORDER, typename S, typename F>
+__host__ __device__ inline void for_each_basis(const S *v, double invh, F &&fn) {
+    if (ORDER == 0) {
+        S t[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) t[k] = k == 0 ? 1.0 : 0.0;
+        fn(0, 1.0, t);
+        return;
+    }
+    const S q1x = (v[2] - v[0]) * invh, q1y = (v[3] - v[1]) * invh;
+    const S q2x = (v[4] - v[0]) * invh, q2y = (v[5] - v[1]) * invh;
+    const S det = q1x * q2y - q1y * q2x;
+    if (det == 0.0) return;
+    const S id = 1.0 / det;
+    // barycentric coordinates as affine forms in eta (origin at v0)
+    const S l1x = q2y * id, l1y = -q2x * id;
+    const S l2x = -q1y * id, l2y = q1x * id;
+    const S la[3] = {1.0, 0.0, 0.0};
+    const S lx[3] = {-(l1x + l2x), l1x, l2x};
+    const S ly[3] = {-(l1y + l2y), l1y, l2y};
+    S one[10], t1[10], t2[10], t3[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) one[k] = k == 0 ? 1.0 : 0.0;
+    if (ORDER == 1) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            mul_affine(one, la[i], lx[i], ly[i], t1);
+            fn(i, 1.0, t1);
+        }
+        return;
+    }
+    // vertices: lambda (3 lambda - 1)(3 lambda - 2) / 2
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        mul_affine(one, la[i], lx[i], ly[i], t1);
+        mul_affine(t1, 3.0 * la[i] - 1.0, 3.0 * lx[i], 3.0 * ly[i], t2);
+        mul_affine(t2, 3.0 * la[i] - 2.0, 3.0 * lx[i], 3.0 * ly[i], t3);
+        fn(i, 0.5, t3);
+    }
+    // edge nodes: 9/2 lambda_a lambda_b (3 lambda_a - 1) at 1/3 from a,
+    //             9/2 lambda_a lambda_b (3 lambda_b - 1) at 2/3 from a
+#pragma unroll
+    for (int ed = 0; ed < 3; ++ed) {
+        const int a = ed, b = (ed + 1) % 3;
+        mul_affine(one, la[a], lx[a], ly[a], t1);
+        mul_affine(t1, la[b], lx[b], ly[b], t2);
+        mul_affine(t2, 3.0 * la[a] - 1.0, 3.0 * lx[a], 3.0 * ly[a], t3);
+        fn(3 + 2 * ed, 4.5, t3);
+        mul_affine(t2, 3.0 * la[b] - 1.0, 3.0 * lx[b], 3.0 * ly[b], t3);
+        fn(4 + 2 * ed, 4.5, t3);
+    }
+    // centroid: 27 lambda_0 lambda_1 lambda_2
+    mul_affine(one, la[0], lx[0], ly[0], t1);
+    mul_affine(t1, la[1], lx[1], ly[1], t2);
+    mul_affine(t2, la[2], lx[2], ly[2], t3);
+    fn(9, 27.0, t3);
+}
+
 // One record: vertices v[6] (world units) and nodal values A[n_nodes] ->
 // rec[16] = v, then e_ij of A(v0 + h eta) = sum e_ij eta_x^i eta_y^j.
 template <int ORDER, typename S>
@@ -63,67 +125,32 @@ __host__ __device__ inline void prepare_record(const S *v, const S *A, double in
     S e[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) e[k] = 0.0;
-    if (ORDER == 0) {
-        e[0] = A[0];
-    } else {
-        const S q1x = (v[2] - v[0]) * invh, q1y = (v[3] - v[1]) * invh;
-        const S q2x = (v[4] - v[0]) * invh, q2y = (v[5] - v[1]) * invh;
-        const S det = q1x * q2y - q1y * q2x;
-        if (det != 0.0) {
-            const S id = 1.0 / det;
-            // barycentric coordinates as affine forms in eta (origin at v0)
-            const S l1x = q2y * id, l1y = -q2x * id;
-            const S l2x = -q1y * id, l2y = q1x * id;
-            const S la[3] = {1.0, 0.0, 0.0};
-            const S lx[3] = {-(l1x + l2x), l1x, l2x};
-            const S ly[3] = {-(l1y + l2y), l1y, l2y};
-            if (ORDER == 1) {
+    for_each_basis<ORDER, S>(v, invh, [&](int i, double w, const S *t) {
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    e[0] += A[i] * la[i];
-                    e[1] += A[i] * lx[i];
-                    e[2] += A[i] * ly[i];
-                }
-            } else {
-                S one[10], t1[10], t2[10], t3[10];
-#pragma unroll
-                for (int k = 0; k < 10; ++k) one[k] = k == 0 ? 1.0 : 0.0;
-                // vertices: lambda (3 lambda - 1)(3 lambda - 2) / 2
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    mul_affine(one, la[i], lx[i], ly[i], t1);
-                    mul_affine(t1, 3.0 * la[i] - 1.0, 3.0 * lx[i], 3.0 * ly[i], t2);
-                    mul_affine(t2, 3.0 * la[i] - 2.0, 3.0 * lx[i], 3.0 * ly[i], t3);
-#pragma unroll
-                    for (int k = 0; k < 10; ++k) e[k] += 0.5 * A[i] * t3[k];
-                }
-                // edge nodes: 9/2 lambda_a lambda_b (3 lambda_a - 1) at 1/3 from a,
-                //             9/2 lambda_a lambda_b (3 lambda_b - 1) at 2/3 from a
-#pragma unroll
-                for (int ed = 0; ed < 3; ++ed) {
-                    const int a = ed, b = (ed + 1) % 3;
-                    mul_affine(one, la[a], lx[a], ly[a], t1);
-                    mul_affine(t1, la[b], lx[b], ly[b], t2);
-                    mul_affine(t2, 3.0 * la[a] - 1.0, 3.0 * lx[a], 3.0 * ly[a], t3);
-#pragma unroll
-                    for (int k = 0; k < 10; ++k) e[k] += 4.5 * A[3 + 2 * ed] * t3[k];
-                    mul_affine(t2, 3.0 * la[b] - 1.0, 3.0 * lx[b], 3.0 * ly[b], t3);
-#pragma unroll
-                    for (int k = 0; k < 10; ++k) e[k] += 4.5 * A[4 + 2 * ed] * t3[k];
-                }
-                // centroid: 27 lambda_0 lambda_1 lambda_2
-                mul_affine(one, la[0], lx[0], ly[0], t1);
-                mul_affine(t1, la[1], lx[1], ly[1], t2);
-                mul_affine(t2, la[2], lx[2], ly[2], t3);
-#pragma unroll
-                for (int k = 0; k < 10; ++k) e[k] += 27.0 * A[9] * t3[k];
-            }
-        }
-    }
+        for (int k = 0; k < 10; ++k) e[k] += w * A[i] * t[k];
+    });
 #pragma unroll
     for (int k = 0; k < 6; ++k) r[k] = v[k];
 #pragma unroll
     for (int k = 0; k < 10; ++k) r[6 + k] = e[k];
+}
+
+// Transpose of the field preparation: for weights g on the coefficients e_ij,
+// gA[i] = sum_ij g_ij d e_ij / d A_i (the basis function's coefficients
+// dotted with g).
+template <int ORDER, typename S>
+__host__ __device__ inline void prepare_record_T(const S *v, const S *g, double invh, S *gA) {
+    constexpr int NN = ORDER == 0 ? 1 : (ORDER == 1 ? 3 : 10);
+#pragma unroll
+    for (int i = 0; i < NN; ++i) gA[i] = 0.0;
+    for_each_basis<ORDER, S>(v, invh, [&](int i, double w, const S *t) {
+        S d = 0.0;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) d += t[k] * g[k];
+#pragma unroll
+        for (int n = 0; n < NN; ++n)
+            if (n == i) gA[n] = w * d;
+    });
 }
 
 // ----------------------------------------------------------------------------
@@ -212,12 +239,73 @@ __host__ __device__ inline void taylor_shift(const S *__restrict__ e, S sx, S sy
         }
 }
 
-// One edge of the signed fan, one kernel piece of radius R.  Adds the
-// edge-frame value and gradient integrals (without c_d and without the
-// -1/h of the gradient).
-template <int DEG, int ORDER, typename S, typename M>
-__host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc, S p, S ya, S yb,
-                                           const Harm<S> *hv, S &oI, S &oX, S &oY) {
+// Consumers of the per-edge closed forms.  edge_piece() hands each one the
+// edge-frame integrals of every harmonic slot: the sector parts (angular
+// terms times the unit-sector radial integrals sv, sw) and the triangle parts
+// (value harmonics n = m, m-2, ... and gradient harmonics n = m+1, m-1, ...
+// of the degree-m part of the field).
+//
+// FieldSink contracts them with one field's edge-frame harmonics hv and adds
+// the value and gradient integrals (without c_d and the -1/h of the
+// gradient).
+template <typename S>
+struct FieldSink {
+    const Harm<S> *hv;
+    S I, X, Y;
+    Harm<S> hx, hy;
+    __host__ __device__ void sector(int m, double sv, double sw, const S *angc, const S *angs) {
+        Harm<S> gx, gy;
+        mul_cs(m, hv[m], gx, gy);
+#pragma unroll
+        for (int n = m & 1; n <= m; n += 2) I += sv * (hv[m].c[n] * angc[n] + hv[m].s[n] * angs[n]);
+#pragma unroll
+        for (int n = (m + 1) & 1; n <= m + 1; n += 2) {
+            X += sw * (gx.c[n] * angc[n] + gx.s[n] * angs[n]);
+            Y += sw * (gy.c[n] * angc[n] + gy.s[n] * angs[n]);
+        }
+    }
+    __host__ __device__ void begin(int m) { mul_cs(m, hv[m], hx, hy); }
+    __host__ __device__ void value(int m, int n, S vc, S vs) { I += hv[m].c[n] * vc + hv[m].s[n] * vs; }
+    __host__ __device__ void grad(int, int n, S wc, S ws) {
+        X += hx.c[n] * wc + hx.s[n] * ws;
+        Y += hy.c[n] * wc + hy.s[n] * ws;
+    }
+};
+
+// BasisSink keeps the integrals themselves, summed over the kernel pieces:
+// vb[m] for the value slots and gb[m] for the gradient slots.  Every
+// quantity of the pair that is linear in the field is a dot product of these
+// with the field's harmonics (the adjoint uses this to get the moments of all
+// monomials at the cost of one evaluation).
+template <int ORDER, typename S>
+struct BasisSink {
+    Harm<S> vb[ORDER + 1], gb[ORDER + 1];
+    __host__ __device__ void sector(int m, double sv, double sw, const S *angc, const S *angs) {
+#pragma unroll
+        for (int n = m & 1; n <= m; n += 2) {
+            vb[m].c[n] += sv * angc[n];
+            vb[m].s[n] += sv * angs[n];
+        }
+#pragma unroll
+        for (int n = (m + 1) & 1; n <= m + 1; n += 2) {
+            gb[m].c[n] += sw * angc[n];
+            gb[m].s[n] += sw * angs[n];
+        }
+    }
+    __host__ __device__ void begin(int) {}
+    __host__ __device__ void value(int m, int n, S vc, S vs) {
+        vb[m].c[n] += vc;
+        vb[m].s[n] += vs;
+    }
+    __host__ __device__ void grad(int m, int n, S wc, S ws) {
+        gb[m].c[n] += wc;
+        gb[m].s[n] += ws;
+    }
+};
+
+// One edge of the signed fan, one kernel piece of radius R, handed to a sink.
+template <int DEG, int ORDER, typename S, typename M, typename Sink>
+__host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc, S p, S ya, S yb, Sink &sink) {
     constexpr int HMAX = DEG + ORDER + 1;
     constexpr int PMAX = DEG + ORDER;
     const double R = K.R[pc];
@@ -255,22 +343,11 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
             dn1 = dn; tn1 = tn; dn = dn2; tn = tn2;
         }
     }
-    // contract the sector parts now, so that the angular terms are dead
+    // hand over the sector parts now, so that the angular terms are dead
     // before the radial terms are formed
     if (clipA || clipB) {
 #pragma unroll
-        for (int m = 0; m <= ORDER; ++m) {
-            Harm<S> hx, hy;
-            mul_cs(m, hv[m], hx, hy);
-            const double sv = K.sv[pc][m], sw = K.sw[pc][m];
-#pragma unroll
-            for (int n = m & 1; n <= m; n += 2) oI += sv * (hv[m].c[n] * angc[n] + hv[m].s[n] * angs[n]);
-#pragma unroll
-            for (int n = (m + 1) & 1; n <= m + 1; n += 2) {
-                oX += sw * (hx.c[n] * angc[n] + hx.s[n] * angs[n]);
-                oY += sw * (hy.c[n] * angc[n] + hy.s[n] * angs[n]);
-            }
-        }
+        for (int m = 0; m <= ORDER; ++m) sink.sector(m, K.sv[pc][m], K.sw[pc][m], angc, angs);
     }
 
     // ---- triangle parts: radial 2F1 terms H_c and powers P_e
@@ -309,8 +386,7 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
 
 #pragma unroll
     for (int m = 0; m <= ORDER; ++m) {
-        Harm<S> hx, hy;
-        mul_cs(m, hv[m], hx, hy);
+        sink.begin(m);
         // kernel-contracted radial sums
         S Ac[ORDER + 1], As[ORDER + 1], Bc[ORDER + 2], Bs[ORDER + 1];
 #pragma unroll
@@ -351,7 +427,7 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
 #pragma unroll
             for (int j = 0; j < n; ++j)
                 if (chebU(n - 1, j) != 0.0) vs = fma(lit(chebU(n - 1, j)) * pj[j], As[j], vs);
-            oI += hv[m].c[n] * vc + hv[m].s[n] * vs;
+            sink.value(m, n, vc, vs);
         }
         // gradient harmonics n = m+1, m-1, ...
 #pragma unroll
@@ -363,9 +439,44 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
 #pragma unroll
             for (int j = 0; j < n; ++j)
                 if (chebU(n - 1, j) != 0.0) ws = fma(lit(chebU(n - 1, j)) * pj[j], Bs[j], ws);
-            oX += hx.c[n] * wc + hx.s[n] * ws;
-            oY += hy.c[n] * wc + hy.s[n] * ws;
+            sink.grad(m, n, wc, ws);
         }
+    }
+}
+
+// Frame of the fan edge from a to b (particle at the origin, units of h):
+// distance p of the edge line, unit normal n towards it, along-edge
+// coordinates ya, yb of the ends from the foot of the perpendicular.  False
+// for an edge of zero length or a fan triangle of zero area.
+template <typename S, typename M>
+__host__ __device__ inline bool edge_frame(const M &math, S axa, S aya, S axb, S ayb, S &p, S &nx, S &ny, S &ya,
+                                           S &yb) {
+    const S Lx = axb - axa, Ly = ayb - aya;
+    const S len2 = Lx * Lx + Ly * Ly;
+    if (len2 == 0.0) return false;
+    S len, il;
+    math.edge_norm(len2, len, il);
+    const S tx = Lx * il, ty = Ly * il;
+    const S sd = axa * ty - aya * tx;        // signed distance of the edge line
+    p = fabs(sd);
+    if (p == 0.0) return false;
+    nx = sd > 0.0 ? ty : S(-ty);
+    ny = sd > 0.0 ? S(-tx) : tx;
+    ya = -axa * ny + aya * nx;
+    yb = sd > 0.0 ? S(ya + len) : S(ya - len);
+    return true;
+}
+
+// cos(n phi), sin(n phi) for n <= 3, (cos phi, sin phi) = (nx, ny): the edge
+// frame is rotated by phi, and a harmonic of order n by n phi.
+template <typename S>
+__host__ __device__ inline void edge_phases(S nx, S ny, S *cph, S *sph) {
+    cph[0] = 1.0; sph[0] = 0.0;
+    cph[1] = nx; sph[1] = ny;
+#pragma unroll
+    for (int n = 2; n <= 3; ++n) {
+        cph[n] = 2.0 * nx * cph[n - 1] - cph[n - 2];
+        sph[n] = 2.0 * nx * sph[n - 1] - sph[n - 2];
     }
 }
 
@@ -408,33 +519,17 @@ __host__ __device__ inline void pair_core(const KArgs &K, const M &math, double 
     S x0 = ax[0], y0 = ay[0], x1 = ax[1], y1 = ay[1], x2 = ax[2], y2 = ay[2];
 #pragma unroll EDGE_UNROLL
     for (int e = 0; e < 3; ++e) {
-        const S axe = x0, aye = y0;
-        const S Lx = x1 - axe, Ly = y1 - aye;
+        const S xa = x0, ya0 = y0, xb = x1, yb0 = y1;
         {
             const S rx = x0, ry = y0;
             x0 = x1; y0 = y1; x1 = x2; y1 = y2; x2 = rx; y2 = ry;
         }
-        const S len2 = Lx * Lx + Ly * Ly;
-        if (len2 == 0.0) continue;
-        S len, il;
-        math.edge_norm(len2, len, il);
-        const S tx = Lx * il, ty = Ly * il;
-        const S sd = axe * ty - aye * tx;        // signed distance of the edge line
-        const S p = fabs(sd);
-        if (p == 0.0) continue;                       // fan triangle of zero area
-        const S nx = sd > 0.0 ? ty : S(-ty), ny = sd > 0.0 ? S(-tx) : tx;
-        const S ya = -axe * ny + aye * nx;       // along-edge coordinates from the foot
-        const S yb = sd > 0.0 ? S(ya + len) : S(ya - len);
+        S p, nx, ny, ya, yb;
+        if (!edge_frame(math, xa, ya0, xb, yb0, p, nx, ny, ya, yb)) continue;
         // harmonics in the edge frame: theta = psi + phi, (cos phi, sin phi) = n
-        Harm<S> hl[ORDER + 1];
         S cph[4], sph[4];
-        cph[0] = 1.0; sph[0] = 0.0;
-        cph[1] = nx; sph[1] = ny;
-#pragma unroll
-        for (int n = 2; n <= 3; ++n) {
-            cph[n] = 2.0 * nx * cph[n - 1] - cph[n - 2];
-            sph[n] = 2.0 * nx * sph[n - 1] - sph[n - 2];
-        }
+        edge_phases(nx, ny, cph, sph);
+        Harm<S> hl[ORDER + 1];
 #pragma unroll
         for (int m = 0; m <= ORDER; ++m)
 #pragma unroll
@@ -444,17 +539,146 @@ __host__ __device__ inline void pair_core(const KArgs &K, const M &math, double 
                 hl[m].c[n] = hc * cph[n] + hs * sph[n];
                 hl[m].s[n] = hs * cph[n] - hc * sph[n];
             }
-        S eI = 0.0, eX = 0.0, eY = 0.0;
+        FieldSink<S> sk;
+        sk.hv = hl;
+        sk.I = sk.X = sk.Y = 0.0;
         const auto em = math.for_edge(p, tau);
-        for (int pc = 0; pc < K.npieces; ++pc) edge_piece<DEG, ORDER, S>(K, em, pc, p, ya, yb, hl, eI, eX, eY);
-        I += eI;
-        GX += eX * nx - eY * ny;
-        GY += eX * ny + eY * nx;
+        for (int pc = 0; pc < K.npieces; ++pc) edge_piece<DEG, ORDER, S>(K, em, pc, p, ya, yb, sk);
+        I += sk.I;
+        GX += sk.X * nx - sk.Y * ny;
+        GY += sk.X * ny + sk.Y * nx;
     }
     const double sg = area2 > 0.0 ? K.cd : -K.cd;
     oI = sg * I;
     oX = -sg * invh * GX;
     oY = -sg * invh * GY;
+}
+
+// ----------------------------------------------------------------------------
+// adjoint of the pair with respect to the field
+// ----------------------------------------------------------------------------
+
+// Transpose of mul_cs: weights x, y on the harmonics of A_m cos(psi) and
+// A_m sin(psi) -> weights added to the harmonic slots of A_m.
+template <typename S>
+__host__ __device__ inline void mul_cs_T(int M, const Harm<S> &x, const Harm<S> &y, Harm<S> &d) {
+#pragma unroll
+    for (int n = M & 1; n <= M; n += 2) {
+        if (n == 0) {
+            d.c[0] += x.c[1] + y.s[1];
+        } else {
+            const S ys = n > 1 ? y.s[n - 1] : S(0.0), xs = n > 1 ? x.s[n - 1] : S(0.0);
+            d.c[n] += 0.5 * (x.c[n + 1] + x.c[n - 1] + y.s[n + 1] - ys);
+            d.s[n] += 0.5 * (x.s[n + 1] + xs + y.c[n - 1] - y.c[n + 1]);
+        }
+    }
+}
+
+// Transpose of taylor_shift: weights g on the coefficients about the particle
+// -> weights ge on the record's coefficients about vertex 0.
+template <int ORDER, typename S>
+__host__ __device__ inline void taylor_shift_T(const S *g, S sx, S sy, S *ge) {
+    const S mx[4] = {1.0, -sx, sx * sx, -sx * sx * sx};
+    const S my[4] = {1.0, -sy, sy * sy, -sy * sy * sy};
+    constexpr double B[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+#pragma unroll
+    for (int k = 0; k < 10; ++k) ge[k] = 0.0;
+#pragma unroll
+    for (int mi = 0; mi <= ORDER; ++mi)
+#pragma unroll
+        for (int j = 0; j <= mi; ++j) {
+            const int i = mi - j;
+            S acc = 0.0;
+#pragma unroll
+            for (int a = 0; a <= i; ++a)
+#pragma unroll
+                for (int b = 0; b <= j; ++b) {
+                    const double w = B[i][a] * B[j][b];
+                    const S f = w == 1.0 ? g[pidx(a, b)] : S(g[pidx(a, b)] * lit(w));
+                    acc += f * mx[i - a] * my[j - b];
+                }
+            ge[pidx(i, j)] = acc;
+        }
+}
+
+// Moments mom[k] = int_T xi^k Phi dxi (record order of the monomials about the
+// particle, xi in units of h, with the c_d and 1/h factors of pair_core) of the
+// cotangent-weighted kernel Phi = cI W + cX dW/dx_p + cY dW/dy_p; that is,
+// mom[k] = cI oI + cX oX + cY oY of pair_core for the unit monomial field k.
+// pair_core is linear in the field's harmonics, so one pass collects, per
+// edge, the closed-form integrals of every harmonic slot (BasisSink), weights
+// them with the cotangents, and carries the weights back through the product
+// with (cos, sin), the edge rotation and the monomial-to-harmonic map.
+template <int DEG, int ORDER, int EDGE_UNROLL = 3>
+__device__ inline void pair_dual(const KArgs &K, const double *ax, const double *ay, double area2, double invh,
+                                 double cI, double cX, double cY, double *mom) {
+    using S = double;
+    const ExactMath math;
+    Harm<S> dg[ORDER + 1];          // weights of the global-frame harmonics
+#pragma unroll
+    for (int m = 0; m <= ORDER; ++m)
+#pragma unroll
+        for (int n = 0; n < 5; ++n) dg[m].c[n] = dg[m].s[n] = 0.0;
+    S x0 = ax[0], y0 = ay[0], x1 = ax[1], y1 = ay[1], x2 = ax[2], y2 = ay[2];
+#pragma unroll EDGE_UNROLL
+    for (int e = 0; e < 3; ++e) {
+        const S xa = x0, ya0 = y0, xb = x1, yb0 = y1;
+        {
+            const S rx = x0, ry = y0;
+            x0 = x1; y0 = y1; x1 = x2; y1 = y2; x2 = rx; y2 = ry;
+        }
+        S p, nx, ny, ya, yb;
+        if (!edge_frame(math, xa, ya0, xb, yb0, p, nx, ny, ya, yb)) continue;
+        BasisSink<ORDER, S> sk;
+#pragma unroll
+        for (int m = 0; m <= ORDER; ++m)
+#pragma unroll
+            for (int n = 0; n < 5; ++n) sk.vb[m].c[n] = sk.vb[m].s[n] = sk.gb[m].c[n] = sk.gb[m].s[n] = 0.0;
+        for (int pc = 0; pc < K.npieces; ++pc) edge_piece<DEG, ORDER, S>(K, math, pc, p, ya, yb, sk);
+        // the edge's share of cI I + cX GX + cY GY in the edge frame:
+        // cI eI - (1/h) (gn eX + gt eY), (gn, gt) = cotangent in (n, t)
+        const S wX = -invh * (cX * nx + cY * ny), wY = -invh * (cY * nx - cX * ny);
+        S cph[4], sph[4];
+        edge_phases(nx, ny, cph, sph);
+#pragma unroll
+        for (int m = 0; m <= ORDER; ++m) {
+            Harm<S> gx, gy, d;
+#pragma unroll
+            for (int n = 0; n < 5; ++n) {
+                gx.c[n] = wX * sk.gb[m].c[n];
+                gx.s[n] = wX * sk.gb[m].s[n];
+                gy.c[n] = wY * sk.gb[m].c[n];
+                gy.s[n] = wY * sk.gb[m].s[n];
+                d.c[n] = cI * sk.vb[m].c[n];
+                d.s[n] = cI * sk.vb[m].s[n];
+            }
+            mul_cs_T(m, gx, gy, d);
+            // transpose of the rotation into the edge frame
+#pragma unroll
+            for (int n = m & 1; n <= m; n += 2) {
+                dg[m].c[n] += d.c[n] * cph[n] - d.s[n] * sph[n];
+                dg[m].s[n] += d.c[n] * sph[n] + d.s[n] * cph[n];
+            }
+        }
+    }
+    // transpose of global_harmonics, times the orientation sign and c_d
+    const double sg = area2 > 0.0 ? K.cd : -K.cd;
+    mom[0] = sg * dg[0].c[0];
+    if (ORDER >= 1) {
+        mom[pidx(1, 0)] = sg * dg[1].c[1];
+        mom[pidx(0, 1)] = sg * dg[1].s[1];
+    }
+    if (ORDER >= 2) {
+        mom[pidx(2, 0)] = 0.5 * sg * (dg[2].c[0] + dg[2].c[2]);
+        mom[pidx(0, 2)] = 0.5 * sg * (dg[2].c[0] - dg[2].c[2]);
+        mom[pidx(1, 1)] = 0.5 * sg * dg[2].s[2];
+    }
+    if (ORDER >= 3) {
+        mom[pidx(3, 0)] = lit(0.25) * sg * fma(lit(3.0), dg[3].c[1], dg[3].c[3]);
+        mom[pidx(1, 2)] = lit(0.25) * sg * (dg[3].c[1] - dg[3].c[3]);
+        mom[pidx(2, 1)] = lit(0.25) * sg * (dg[3].s[1] + dg[3].s[3]);
+        mom[pidx(0, 3)] = lit(0.25) * sg * fma(lit(3.0), dg[3].s[1], -dg[3].s[3]);
+    }
 }
 
 }  // namespace sphbi
