@@ -187,6 +187,22 @@ __host__ __device__ inline void mul_cs(int M, const Harm<S> &v, Harm<S> &x, Harm
     }
 }
 
+// Transpose of mul_cs: weights x, y on the harmonics of A_m cos(psi) and
+// A_m sin(psi) -> weights added to the harmonic slots of A_m.
+template <typename S>
+__host__ __device__ inline void mul_cs_T(int M, const Harm<S> &x, const Harm<S> &y, Harm<S> &d) {
+#pragma unroll
+    for (int n = M & 1; n <= M; n += 2) {
+        if (n == 0) {
+            d.c[0] += x.c[1] + y.s[1];
+        } else {
+            const S ys = n > 1 ? y.s[n - 1] : S(0.0), xs = n > 1 ? x.s[n - 1] : S(0.0);
+            d.c[n] += 0.5 * (x.c[n + 1] + x.c[n - 1] + y.s[n + 1] - ys);
+            d.s[n] += 0.5 * (x.s[n + 1] + xs + y.c[n - 1] - y.c[n + 1]);
+        }
+    }
+}
+
 template <int ORDER, typename S>
 __host__ __device__ inline void global_harmonics(const S *c, Harm<S> *h) {
 #pragma unroll
@@ -314,38 +330,47 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
     const bool clipA = aya > yc, clipB = ayb > yc;
 
     // ---- sector parts of clipped endpoints (cone formulas, Sec. 5.2)
+    // angc[n], angs[n]: integrals of cos(n psi), sin(n psi) over the sector
+    // angles of both ends, Q(y_b) - Q(y_a); each end contributes the part at
+    // its own ray and the part at the circle crossing psi_c, which is shared.
     S angc[5], angs[5];
 #pragma unroll
     for (int n = 0; n < 5; ++n) angc[n] = angs[n] = 0.0;
-    const S cpc = p < R ? S(p * K.iR[pc]) : S(1.0), spc = p < R ? S(yc * K.iR[pc]) : S(0.0);   // (cos, sin) psi_c
+    if (clipA || clipB) {
+        double wc = 0.0, ws = 0.0;                    // sums of the ends' signs
 #pragma unroll
-    for (int end = 0; end < 2; ++end) {
-        const bool clip = end ? clipB : clipA;
-        if (!clip) continue;
-        const S y = end ? yb : ya, ay = end ? ayb : aya;
-        const double sg = end ? 1.0 : -1.0;          // Q(y_b) - Q(y_a)
-        const double sy = y > 0.0 ? sg : -sg;          // odd cosine part
-        S ir, ang;
-        math.sector_seed(p, ay, yc, ir, ang);
-        const S cu = p * ir, su = ay * ir;
-        angc[0] += sy * ang;
-        S cn1 = 1.0, sn1 = 0.0, cn = cu, sn = su;      // cos/sin of n u
-        S dn1 = 1.0, tn1 = 0.0, dn = cpc, tn = spc;    // cos/sin of n psi_c
+        for (int end = 0; end < 2; ++end) {
+            const bool clip = end ? clipB : clipA;
+            if (!clip) continue;
+            const S y = end ? yb : ya, ay = end ? ayb : aya;
+            const double sg = end ? 1.0 : -1.0;          // Q(y_b) - Q(y_a)
+            const double sy = y > 0.0 ? sg : -sg;          // odd cosine part
+            wc += sy;
+            ws += sg;
+            S ir, ang;
+            math.sector_seed(p, ay, yc, ir, ang);
+            const S cu = p * ir, su = ay * ir;
+            angc[0] += sy * ang;
+            S cn1 = 1.0, sn1 = 0.0, cn = cu, sn = su;      // cos/sin of n u
+#pragma unroll
+            for (int n = 1; n <= ORDER + 1; ++n) {
+                const double inv = lit(1.0 / n);
+                angc[n] += sn * (sy * inv);
+                angs[n] -= cn * (sg * inv);
+                const S cn2 = 2.0 * cu * cn - cn1, sn2 = 2.0 * cu * sn - sn1;
+                cn1 = cn; sn1 = sn; cn = cn2; sn = sn2;
+            }
+        }
+        const S cpc = p * K.iR[pc], spc = yc * K.iR[pc];    // (cos, sin) psi_c
+        S dn1 = 1.0, tn1 = 0.0, dn = cpc, tn = spc;        // cos/sin of n psi_c
 #pragma unroll
         for (int n = 1; n <= ORDER + 1; ++n) {
             const double inv = lit(1.0 / n);
-            const double sinv = sy * inv, ginv = sg * inv;
-            angc[n] += (sn - tn) * sinv;
-            angs[n] += (dn - cn) * ginv;
-            const S cn2 = 2.0 * cu * cn - cn1, sn2 = 2.0 * cu * sn - sn1;
+            angc[n] -= tn * (wc * inv);
+            angs[n] += dn * (ws * inv);
             const S dn2 = 2.0 * cpc * dn - dn1, tn2 = 2.0 * cpc * tn - tn1;
-            cn1 = cn; sn1 = sn; cn = cn2; sn = sn2;
             dn1 = dn; tn1 = tn; dn = dn2; tn = tn2;
         }
-    }
-    // hand over the sector parts now, so that the angular terms are dead
-    // before the radial terms are formed
-    if (clipA || clipB) {
 #pragma unroll
         for (int m = 0; m <= ORDER; ++m) sink.sector(m, K.sv[pc][m], K.sw[pc][m], angc, angs);
     }
@@ -557,22 +582,6 @@ __host__ __device__ inline void pair_core(const KArgs &K, const M &math, double 
 // ----------------------------------------------------------------------------
 // adjoint of the pair with respect to the field
 // ----------------------------------------------------------------------------
-
-// Transpose of mul_cs: weights x, y on the harmonics of A_m cos(psi) and
-// A_m sin(psi) -> weights added to the harmonic slots of A_m.
-template <typename S>
-__host__ __device__ inline void mul_cs_T(int M, const Harm<S> &x, const Harm<S> &y, Harm<S> &d) {
-#pragma unroll
-    for (int n = M & 1; n <= M; n += 2) {
-        if (n == 0) {
-            d.c[0] += x.c[1] + y.s[1];
-        } else {
-            const S ys = n > 1 ? y.s[n - 1] : S(0.0), xs = n > 1 ? x.s[n - 1] : S(0.0);
-            d.c[n] += 0.5 * (x.c[n + 1] + x.c[n - 1] + y.s[n + 1] - ys);
-            d.s[n] += 0.5 * (x.s[n + 1] + xs + y.c[n - 1] - y.c[n + 1]);
-        }
-    }
-}
 
 // Transpose of taylor_shift: weights g on the coefficients about the particle
 // -> weights ge on the record's coefficients about vertex 0.

@@ -1,7 +1,8 @@
 // Precision policies for the transcendental steps of one pair evaluation.
 //
 // ExactMath evaluates every square root, reciprocal, logarithm and arctangent
-// in the working type (double, or a dual number in the adjoint).
+// in FP64 (square roots from the hardware estimate and Newton steps, within
+// an ulp of the correctly rounded ones).
 //
 // MixedMath runs them on the FP32 hardware units instead:
 //   * sqrt, 1/sqrt and 1/x start from the FP32 estimate and take one Newton
@@ -33,27 +34,41 @@
 
 namespace sphbi {
 
+// FP64 1/sqrt(x) and sqrt(x) for finite x > 0 from the hardware estimate and
+// two Newton steps (about 10 instructions instead of the 33 of the library's
+// correctly rounded 1.0 / sqrt(x); measured within 1 ulp of it).  Arguments
+// below 2^-960 are scaled by 2^512 first so that the estimate stays normal.
+__device__ inline double rsqrt_nr(double x) {
+    const bool tiny = x < 0x1p-960;
+    const double xs = tiny ? x * 0x1p512 : x;
+    double r = __builtin_amdgcn_rsq(xs);
+    double e = fma(-xs * r, r, 1.0);
+    r = fma(0.5 * r, e, r);
+    e = fma(-xs * r, r, 1.0);
+    r = fma(0.5 * r, e, r);
+    return tiny ? r * 0x1p256 : r;
+}
+__device__ inline double sqrt_nr(double x) {
+    const double r = rsqrt_nr(x);
+    const double s = x * r;
+    return fma(0.5 * r, fma(-s, s, x), s);
+}
+
 struct ExactMath {
-    template <typename S>
-    __host__ __device__ S sqrt_(const S &x) const { return sqrt(x); }
-    template <typename S>
-    __host__ __device__ S rsqrt_(const S &x) const { return 1.0 / sqrt(x); }
-    template <typename S>
-    __host__ __device__ S rcp_(const S &x) const { return 1.0 / x; }
+    __device__ double sqrt_(double x) const { return x > 0.0 ? sqrt_nr(x) : 0.0; }
+    __device__ double rsqrt_(double x) const { return rsqrt_nr(x); }
+    __device__ double rcp_(double x) const { return 1.0 / x; }
     // angular terms of one clipped endpoint: 1/sqrt(p^2 + y^2) and the angle
     // between the endpoint ray and the circle crossing psi_c
-    template <typename S>
-    __host__ __device__ void sector_seed(const S &p, const S &ay, const S &yc, S &ir, S &ang) const {
-        ir = 1.0 / sqrt(p * p + ay * ay);
+    __device__ void sector_seed(double p, double ay, double yc, double &ir, double &ang) const {
+        ir = rsqrt_nr(p * p + ay * ay);
         ang = atan2_q1(p * (ay - yc), p * p + ay * yc);     // both arguments >= 0, the second > 0
     }
     // H_0 = asinh(yB/p) - asinh(yA/p), with asinh(|y|/p) = log((|y| + rho)/p):
     // one quotient and one logarithm whichever signs the ends have
-    template <typename S>
-    __host__ __device__ S h0(const S &p, const S &yA, const S &yB, const S &rA, const S &rB) const {
-        const S gA = fabs(yA) + rA, gB = fabs(yB) + rB;
-        S num, den;
-        double sg;
+    __device__ double h0(double p, double yA, double yB, double rA, double rB) const {
+        const double gA = fabs(yA) + rA, gB = fabs(yB) + rB;
+        double num, den, sg;
         if ((yA < 0.0 && yB > 0.0) || (yA > 0.0 && yB < 0.0)) {
             num = gA * gB;
             den = p * p;
@@ -70,14 +85,12 @@ struct ExactMath {
         return sg * log_pos(num / den);
     }
     // length and inverse length of an edge vector
-    template <typename S>
-    __host__ __device__ void edge_norm(const S &len2, S &len, S &il) const {
-        len = sqrt(len2);
-        il = 1.0 / len;
+    __device__ void edge_norm(double len2, double &len, double &il) const {
+        il = rsqrt_nr(len2);
+        len = len2 * il;
     }
     // policy for one edge at distance p (in units of h) from the particle
-    template <typename S>
-    __host__ __device__ ExactMath for_edge(const S &, double) const { return *this; }
+    __device__ ExactMath for_edge(double, double) const { return *this; }
 };
 
 // FP32 hardware estimates (one instruction each on gfx950).  Arguments are
