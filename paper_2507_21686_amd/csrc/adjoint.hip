@@ -51,7 +51,6 @@ __device__ inline void edge_line(const KArgs &K, double p, double ya, double yb,
                                  double &Ja, double &Jb) {
     constexpr int NP = ORDER + 2;                 // t A has degree ORDER + 1
     constexpr int NQ = ORDER + 3;                 // t A (p gn + y gt) has degree ORDER + 2
-    constexpr int HL = DEG + ORDER + 3;
     Ja = Jb = 0.0;
     // A along the line: xi_x = p nx - y ny, xi_y = p ny + y nx
     double X[4][4], Y[4][4];                      // coefficients of X^i, Y^j in y
@@ -99,84 +98,92 @@ __device__ inline void edge_line(const KArgs &K, double p, double ya, double yb,
     }
     const double lo0 = fmin(ya, yb), hi0 = fmax(ya, yb);
     const double p2 = p * p;
-    for (int pc = 0; pc < K.npieces; ++pc) {
+    // y^a = y^(a mod 2) (rho^2 - p^2)^m, m = a div 2, so every term reduces to
+    // int rho^c dy = H_(c+1) (H_c = int rho^(c-1) dy, the forward pass's radial
+    // terms) and int y rho^c dy = E_(c+2), E_e = (rho_hi^e - rho_lo^e)/e.  With
+    // the kernel folded in first,
+    //   int y^a W dy          = sum_i C(m,i) (-p^2)^(m-i) (a even ? G0[i] : G1[i]),
+    //   int y^a W'/rho dy * h = sum_i C(m,i) (-p^2)^(m-i) (a even ? K0[i] : K1[i]),
+    //   G0[i] = sum_j b_j H_(2i+j+1),  G1[i] = sum_j b_j E_(2i+j+2),
+    //   K0[i] = sum_j j b_j H_(2i+j-1), K1[i] = sum_j j b_j E_(2i+j),
+    // and the sums over j are taken while H and E are generated, so neither is
+    // stored.
+    constexpr int MI = (NQ - 1) / 2;              // largest m
+    constexpr int HL = DEG + 2 * MI + 2;          // largest radial index used
+#pragma unroll
+    for (int pc = 0; pc < 2; ++pc) {
+        if (pc >= K.npieces) break;
         const double R = K.R[pc];
         if (!(p < R)) continue;
-        const double yc = sqrt((R - p) * (R + p));
+        const ExactMath math;
+        const double yc = math.sqrt_((R - p) * (R + p));
         const double lo = fmax(lo0, -yc), hi = fmin(hi0, yc);
         if (!(lo < hi)) continue;
-        const double rl = sqrt(p2 + lo * lo), rh = sqrt(p2 + hi * hi);
-        // H_c = int_lo^hi rho^(c-1) dy; H_0 = asinh(hi/p) - asinh(lo/p), only
-        // ever multiplied by p or p^2, so 0 on a line through the particle
-        double H[HL + 1];
-        if (p > 0.0) {
-            const double fl = fabs(lo) + rl, fh = fabs(hi) + rh;
-            // asinh(y/p) = sign(y) log((|y| + rho)/p)
-            if (lo < 0.0 && hi > 0.0) H[0] = log(fl * fh / p2);
-            else if (hi > 0.0) H[0] = log(fh / fl);
-            else H[0] = log(fl / fh);
-        } else {
-            H[0] = 0.0;
-        }
-        H[1] = hi - lo;
-        double gl = 1.0, gh = 1.0;
+        const double rl = math.sqrt_(p2 + lo * lo), rh = math.sqrt_(p2 + hi * hi);
+        double G0[MI + 1], G1[MI + 1], K0[MI + 1], K1[MI + 1];
 #pragma unroll
-        for (int k = 2; k <= HL; ++k) {
-            gl *= rl;
-            gh *= rh;
-            H[k] = (gh * hi - gl * lo + (k - 1) * p2 * H[k - 2]) * (1.0 / k);
-        }
-        // E_e = int_lo^hi y rho^(e-2) dy = (rh^e - rl^e) / e
-        double E[HL + 1];
-        E[0] = 0.0;
-        double el = 1.0, eh = 1.0;
+        for (int i = 0; i <= MI; ++i) G0[i] = G1[i] = K0[i] = K1[i] = 0.0;
+        // H_0 = asinh(hi/p) - asinh(lo/p), only ever multiplied by p or p^2,
+        // so 0 on a line through the particle
+        const double H0 = p > 0.0 ? math.h0(p, lo, hi, rl, rh) : 0.0;
+        double hm2 = 0.0, hm1 = 0.0;              // H_(c-2), H_(c-1)
+        double gl = 1.0, gh = 1.0;                // rho^(c-1)
+        double el = 1.0, eh = 1.0;                // rho^e
 #pragma unroll
-        for (int e = 1; e <= HL; ++e) {
-            el *= rl;
-            eh *= rh;
-            E[e] = (eh - el) * (1.0 / e);
+        for (int c = 0; c <= HL; ++c) {
+            double Hc;
+            if (c == 0) {
+                Hc = H0;
+            } else if (c == 1) {
+                Hc = hi - lo;
+            } else {
+                gl *= rl;
+                gh *= rh;
+                Hc = (gh * hi - gl * lo + lit(c - 1.0) * p2 * hm2) * lit(1.0 / c);
+            }
+            double Ec = 0.0;
+            if (c >= 1) {
+                el *= rl;
+                eh *= rh;
+                Ec = (eh - el) * lit(1.0 / c);
+            }
+#pragma unroll
+            for (int i = 0; i <= MI; ++i) {
+                const int j0 = c - 2 * i - 1, j1 = c - 2 * i - 2, k0 = c - 2 * i + 1, k1 = c - 2 * i;
+                if (j0 >= 0 && j0 <= DEG) G0[i] = fma(K.b[pc][j0], Hc, G0[i]);
+                if (j1 >= 0 && j1 <= DEG && c >= 1) G1[i] = fma(K.b[pc][j1], Ec, G1[i]);
+                if (k0 >= 1 && k0 <= DEG) K0[i] = fma(lit(k0) * K.b[pc][k0], Hc, K0[i]);
+                if (k1 >= 1 && k1 <= DEG && c >= 1) K1[i] = fma(lit(k1) * K.b[pc][k1], Ec, K1[i]);
+            }
+            hm2 = hm1;
+            hm1 = Hc;
         }
-        // Y(a, cc) = int y^a rho^cc dy, by y^2 = rho^2 - p^2:
-        //   a = 2m:     sum_i C(m,i) (-p^2)^(m-i) H_{2i+cc+1}
-        //   a = 2m+1:   sum_i C(m,i) (-p^2)^(m-i) E_{2i+cc+2}
-        // (a <= 5, so m <= 2 and C(2,1) = 2 is the only coefficient above 1)
-        auto Yac = [&](int a, int cc) -> double {
+        // int y^a (W or W') dy for every power a of the field polynomials
+        auto expand = [&](int a, const double *g0, const double *g1) -> double {
             const int m = a >> 1;
+            const double *g = (a & 1) ? g1 : g0;
             double s = 0.0, pw = 1.0;
 #pragma unroll
             for (int i = 2; i >= 0; --i) {
                 if (i > m) continue;
-                const double w = (m == 2 && i == 1 ? 2.0 : 1.0) * pw;
-                s += w * ((a & 1) ? E[2 * i + cc + 2] : H[2 * i + cc + 1]);
+                const double w = (m == 2 && i == 1 ? 2.0 : 1.0) * pw;    // C(m, i), m <= 2
+                s = fma(w, g[i], s);
                 pw *= -p2;
             }
             return s;
         };
         double s1a = 0.0, s1b = 0.0, s2a = 0.0, s2b = 0.0;
 #pragma unroll
-        for (int j = 0; j <= DEG; ++j) {
-            const double bj = K.b[pc][j];
-            if (bj == 0.0) continue;
-            double ya1 = 0.0, yb1 = 0.0;
+        for (int a = 0; a < NP; ++a) {
+            const double y = expand(a, G0, G1);
+            s1a = fma(Pa[a], y, s1a);
+            s1b = fma(Pb[a], y, s1b);
+        }
 #pragma unroll
-            for (int a = 0; a < NP; ++a) {
-                const double y = Yac(a, j);
-                ya1 += Pa[a] * y;
-                yb1 += Pb[a] * y;
-            }
-            s1a += bj * ya1;
-            s1b += bj * yb1;
-            if (j >= 1) {
-                double ya2 = 0.0, yb2 = 0.0;
-#pragma unroll
-                for (int a = 0; a < NQ; ++a) {
-                    const double y = Yac(a, j - 2);
-                    ya2 += Qa[a] * y;
-                    yb2 += Qb[a] * y;
-                }
-                s2a += j * bj * ya2;
-                s2b += j * bj * yb2;
-            }
+        for (int a = 0; a < NQ; ++a) {
+            const double y = expand(a, K0, K1);
+            s2a = fma(Qa[a], y, s2a);
+            s2b = fma(Qb[a], y, s2b);
         }
         const double f = K.cd * invh;
         Ja += f * (gI * s1a - invh * s2a);

@@ -643,7 +643,11 @@ __device__ inline void pair_dual(const KArgs &K, const double *ax, const double 
         for (int m = 0; m <= ORDER; ++m)
 #pragma unroll
             for (int n = 0; n < 5; ++n) sk.vb[m].c[n] = sk.vb[m].s[n] = sk.gb[m].c[n] = sk.gb[m].s[n] = 0.0;
-        for (int pc = 0; pc < K.npieces; ++pc) edge_piece<DEG, ORDER, S>(K, math, pc, p, ya, yb, sk);
+        // pieces unrolled (at most two): a constant piece index keeps every
+        // coefficient a scalar load from the argument block
+#pragma unroll
+        for (int pc = 0; pc < 2; ++pc)
+            if (pc < K.npieces) edge_piece<DEG, ORDER, S>(K, math, pc, p, ya, yb, sk);
         // the edge's share of cI I + cX GX + cY GY in the edge frame:
         // cI eI - (1/h) (gn eX + gt eY), (gn, gt) = cotangent in (n, t)
         const S wX = -invh * (cX * nx + cY * ny), wY = -invh * (cY * nx - cX * ny);
