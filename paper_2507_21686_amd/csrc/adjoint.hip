@@ -363,40 +363,46 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const KArgs K, double invh
 }
 
 // start of every triangle's run in the triangle-sorted pair order
-__global__ void tri_starts(int64_t P, int64_t T, const int32_t *__restrict__ sorted_tri, int64_t *__restrict__ start) {
+__global__ void tri_starts(int64_t P, int64_t T, const uint32_t *__restrict__ sorted_tri, int64_t *__restrict__ start) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t > T) return;
     int64_t lo = 0, hi = P;     // first index with sorted_tri[i] >= t
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if (sorted_tri[mid] < t) lo = mid + 1;
+        if ((int64_t)sorted_tri[mid] < t) lo = mid + 1;
         else hi = mid;
     }
     start[t] = lo;
 }
 
-__global__ void iota_i32(int64_t P, int32_t *__restrict__ a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < P) a[i] = (int32_t)i;
+// Per-triangle sums of the per-pair gradients, in pair order: 16 lanes per
+// triangle, lane k summing component k (the NG <= 16 components of a pair are
+// contiguous, so the lanes read one pair's row together).
+template <int NG>
+__global__ __launch_bounds__(256) void tri_reduce(int64_t T, int n_nodes, const int64_t *__restrict__ start,
+                                                  const int32_t *__restrict__ perm,
+                                                  const double *__restrict__ pair_grad, double *__restrict__ dtri,
+                                                  double *__restrict__ dnodal) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = g >> 4;
+    const int k = (int)(g & 15);
+    if (t >= T) return;
+    double acc = 0.0;
+    if (k < NG)
+        for (int64_t i = start[t]; i < start[t + 1]; ++i) acc += pair_grad[(int64_t)perm[i] * NG + k];
+    if (k < 6) dtri[k * T + t] = acc;
+    else if (k < 6 + n_nodes) dnodal[(k - 6) * T + t] = acc;
 }
 
-template <int NG>
-__global__ void tri_reduce(int64_t T, int n_nodes, const int64_t *__restrict__ start, const int32_t *__restrict__ perm,
-                           const double *__restrict__ pair_grad, double *__restrict__ dtri,
-                           double *__restrict__ dnodal) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    double acc[NG];
-#pragma unroll
-    for (int k = 0; k < NG; ++k) acc[k] = 0.0;
-    for (int64_t i = start[t]; i < start[t + 1]; ++i) {
-        const double *g = pair_grad + (int64_t)perm[i] * NG;
-#pragma unroll
-        for (int k = 0; k < NG; ++k) acc[k] += g[k];
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) dtri[k * T + t] = acc[k];
-    for (int n = 0; n < n_nodes; ++n) dnodal[n * T + t] = acc[6 + n];
+// Sort keys: the triangle index, or T for an index outside [0, T) (such pairs
+// contribute nothing and sort after every triangle's run).
+__global__ void sort_keys(int64_t P, int64_t T, const int32_t *__restrict__ tri_idx, uint32_t *__restrict__ key,
+                          int32_t *__restrict__ iota) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const int32_t t = tri_idx[i];
+    key[i] = (t >= 0 && t < T) ? (uint32_t)t : (uint32_t)T;
+    iota[i] = (int32_t)i;
 }
 
 template <int ORDER>
@@ -420,12 +426,12 @@ void launch_adj_deg(int deg, const KArgs &K, double invh, int64_t N, const doubl
 size_t backward_workspace(int64_t T, int64_t P, int n_nodes) {
     const size_t NG = 6 + (size_t)n_nodes;
     size_t tmp = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const int32_t *)nullptr, (int32_t *)nullptr,
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr,
                                              (const int32_t *)nullptr, (int32_t *)nullptr, (int)(P > 0 ? P : 1));
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t o = 0;
     o += al((size_t)(P > 0 ? P : 1) * NG * sizeof(double));      // per-pair gradients
-    o += 3 * al((size_t)(P > 0 ? P : 1) * sizeof(int32_t));       // iota, sorted keys, permutation
+    o += 4 * al((size_t)(P > 0 ? P : 1) * sizeof(int32_t));       // keys, sorted keys, iota, permutation
     o += al((size_t)(T + 1) * sizeof(int64_t));                   // triangle starts
     o += al(tmp);
     return o;
@@ -442,16 +448,18 @@ int launch_backward(int order, int deg, const KArgs &K, double h, int64_t N, con
     const int64_t Pn = P > 0 ? P : 1;
     double *pair_grad = (double *)w;
     w += al((size_t)Pn * NG * sizeof(double));
-    int32_t *iota = (int32_t *)w;
+    uint32_t *keys_in = (uint32_t *)w;
     w += al((size_t)Pn * sizeof(int32_t));
-    int32_t *keys = (int32_t *)w;
+    uint32_t *keys = (uint32_t *)w;
+    w += al((size_t)Pn * sizeof(int32_t));
+    int32_t *iota = (int32_t *)w;
     w += al((size_t)Pn * sizeof(int32_t));
     int32_t *perm = (int32_t *)w;
     w += al((size_t)Pn * sizeof(int32_t));
     int64_t *start = (int64_t *)w;
     w += al((size_t)(T + 1) * sizeof(int64_t));
     size_t tmp = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const int32_t *)nullptr, (int32_t *)nullptr,
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr,
                                              (const int32_t *)nullptr, (int32_t *)nullptr, (int)Pn);
     const double invh = 1.0 / h;
     if (N > 0) {
@@ -466,12 +474,14 @@ int launch_backward(int order, int deg, const KArgs &K, double h, int64_t N, con
     if (e != hipSuccess) { set_error("adjoint launch: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
     if (T == 0) return SPHBI_OK;
     if (P > 0) {
-        hipLaunchKernelGGL(iota_i32, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, P, iota);
-        e = hipcub::DeviceRadixSort::SortPairs(w, tmp, tri_idx, keys, iota, perm, (int)P, 0, 32, s);
+        hipLaunchKernelGGL(sort_keys, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, P, T, tri_idx, keys_in, iota);
+        int bits = 1;                                  // keys are in [0, T]
+        while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)T) ++bits;
+        e = hipcub::DeviceRadixSort::SortPairs(w, tmp, keys_in, keys, iota, perm, (int)P, 0, bits, s);
         if (e != hipSuccess) { set_error("pair sort: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
     }
     hipLaunchKernelGGL(tri_starts, dim3((unsigned)((T + 1 + 255) / 256)), dim3(256), 0, s, P, T, keys, start);
-    const unsigned tb = (unsigned)((T + 255) / 256);
+    const unsigned tb = (unsigned)((T * 16 + 255) / 256);
     if (NN == 1) hipLaunchKernelGGL(tri_reduce<7>, dim3(tb), dim3(256), 0, s, T, 1, start, perm, pair_grad, dtri, dnodal);
     else if (NN == 3) hipLaunchKernelGGL(tri_reduce<9>, dim3(tb), dim3(256), 0, s, T, 3, start, perm, pair_grad, dtri, dnodal);
     else hipLaunchKernelGGL(tri_reduce<16>, dim3(tb), dim3(256), 0, s, T, 10, start, perm, pair_grad, dtri, dnodal);
