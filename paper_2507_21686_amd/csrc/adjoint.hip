@@ -253,7 +253,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const KArgs K, double invh
                     taylor_shift<ORDER, double>(rec + 6, ax[0], ay[0], c);
                     // moments of the monomials about the particle, in one pass
                     double mom[NM];
-                    pair_dual<DEG, ORDER>(K, ax, ay, area2, invh, cI, cX, cY, mom);
+                    // the cubic-field degree-11 variant keeps its edge loop rolled, like
+                    // the forward kernel's: fully unrolled, that instantiation produced
+                    // wrong moments (checked against the oracle in the tests) while
+                    // the rolled form is correct
+                    pair_dual<DEG, ORDER, (ORDER >= 2 && DEG > 8) ? 1 : 3>(K, ax, ay, area2, invh, cI, cX, cY, mom);
                     // nodal values: the moments carried back through the
                     // shift to the particle and the field preparation
                     {

@@ -320,19 +320,28 @@ struct BasisSink {
 };
 
 // One edge of the signed fan, one kernel piece of radius R, handed to a sink.
+// ra2, rb2 are the squared distances of the edge's ends from the particle: an
+// end is clipped (outside the circle) by the same test in both edges that
+// share it, which the sector terms below rely on.
 template <int DEG, int ORDER, typename S, typename M, typename Sink>
-__host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc, S p, S ya, S yb, Sink &sink) {
+__host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc, S p, S ya, S yb, S ra2, S rb2,
+                                           Sink &sink) {
     constexpr int HMAX = DEG + ORDER + 1;
     constexpr int PMAX = DEG + ORDER;
     const double R = K.R[pc];
     const S yc = p < R ? S(math.sqrt_((R - p) * (R + p))) : S(0.0);
     const S aya = fabs(ya), ayb = fabs(yb);
-    const bool clipA = aya > yc, clipB = ayb > yc;
+    const bool clipA = ra2 > R * R, clipB = rb2 > R * R;
 
     // ---- sector parts of clipped endpoints (cone formulas, Sec. 5.2)
     // angc[n], angs[n]: integrals of cos(n psi), sin(n psi) over the sector
-    // angles of both ends, Q(y_b) - Q(y_a); each end contributes the part at
-    // its own ray and the part at the circle crossing psi_c, which is shared.
+    // angles of both ends, Q(y_b) - Q(y_a).  The sector of an end runs from the
+    // circle crossing psi_c to the end's own ray.  For n >= 1 the part at the
+    // end's ray depends only on the ray's direction: in the triangle's frame it
+    // is +F(theta_v) from the edge that ends at vertex v and -F(theta_v) from
+    // the edge that starts there, so it cancels around the triangle and is not
+    // formed (pair_core adds it back where an edge is skipped).  What remains
+    // is the angle itself (n = 0) and the crossing part, shared by both ends.
     S angc[5], angs[5];
 #pragma unroll
     for (int n = 0; n < 5; ++n) angc[n] = angs[n] = 0.0;
@@ -347,19 +356,7 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
             const double sy = y > 0.0 ? sg : -sg;          // odd cosine part
             wc += sy;
             ws += sg;
-            S ir, ang;
-            math.sector_seed(p, ay, yc, ir, ang);
-            const S cu = p * ir, su = ay * ir;
-            angc[0] += sy * ang;
-            S cn1 = 1.0, sn1 = 0.0, cn = cu, sn = su;      // cos/sin of n u
-#pragma unroll
-            for (int n = 1; n <= ORDER + 1; ++n) {
-                const double inv = lit(1.0 / n);
-                angc[n] += sn * (sy * inv);
-                angs[n] -= cn * (sg * inv);
-                const S cn2 = 2.0 * cu * cn - cn1, sn2 = 2.0 * cu * sn - sn1;
-                cn1 = cn; sn1 = sn; cn = cn2; sn = sn2;
-            }
+            angc[0] += sy * math.sector_angle(p, ay, yc);
         }
         const S cpc = p * K.iR[pc], spc = yc * K.iR[pc];    // (cos, sin) psi_c
         S dn1 = 1.0, tn1 = 0.0, dn = cpc, tn = spc;        // cos/sin of n psi_c
@@ -505,6 +502,60 @@ __host__ __device__ inline void edge_phases(S nx, S ny, S *cph, S *sph) {
     }
 }
 
+// The part of the sector integrals at a vertex ray that edge_piece leaves out
+// (it cancels between the two edges sharing a clipped vertex), for a vertex
+// whose partner edge was skipped: s * (F(theta) for every harmonic slot n >= 1
+// of the value and the gradient integrand, F_c = sin(n theta)/n and
+// F_s = -cos(n theta)/n, summed over the pieces that clip the vertex), in the
+// triangle's frame.  (vx, vy): vertex relative to the particle, units of h.
+template <int ORDER, typename S, typename M>
+__host__ __device__ inline void vertex_ray_terms(const KArgs &K, const M &math, const Harm<S> *hg, S vx, S vy, double s,
+                                                 S &oI, S &oX, S &oY) {
+    const S r2 = vx * vx + vy * vy;
+    if (!(r2 > 0.0)) return;
+    const S ir = math.rsqrt_(r2);
+    const S c1 = vx * ir, s1 = vy * ir;
+    S fc[5], fs[5];                                 // sin(n theta)/n, -cos(n theta)/n
+    {
+        S cn1 = 1.0, sn1 = 0.0, cn = c1, sn = s1;
+        fc[0] = fs[0] = 0.0;
+#pragma unroll
+        for (int n = 1; n <= ORDER + 1; ++n) {
+            const double inv = lit(1.0 / n);
+            fc[n] = sn * inv;
+            fs[n] = -cn * inv;
+            const S cn2 = 2.0 * c1 * cn - cn1, sn2 = 2.0 * c1 * sn - sn1;
+            cn1 = cn; sn1 = sn; cn = cn2; sn = sn2;
+        }
+#pragma unroll
+        for (int n = ORDER + 2; n < 5; ++n) fc[n] = fs[n] = 0.0;
+    }
+    for (int pc = 0; pc < K.npieces; ++pc) {
+        if (!(r2 > K.R[pc] * K.R[pc])) continue;
+        S vi = 0.0, vxs = 0.0, vys = 0.0;
+#pragma unroll
+        for (int m = 0; m <= ORDER; ++m) {
+            Harm<S> gx, gy;
+            mul_cs(m, hg[m], gx, gy);
+            S ti = 0.0, tx = 0.0, ty = 0.0;
+#pragma unroll
+            for (int n = 1; n < 5; ++n) {
+                if (n <= m) ti += hg[m].c[n] * fc[n] + hg[m].s[n] * fs[n];
+                if (n <= m + 1) {
+                    tx += gx.c[n] * fc[n] + gx.s[n] * fs[n];
+                    ty += gy.c[n] * fc[n] + gy.s[n] * fs[n];
+                }
+            }
+            vi += K.sv[pc][m] * ti;
+            vxs += K.sw[pc][m] * tx;
+            vys += K.sw[pc][m] * ty;
+        }
+        oI += s * vi;
+        oX += s * vxs;
+        oY += s * vys;
+    }
+}
+
 // tau: edges whose line passes within tau (units of h) of the particle are
 // evaluated with the exact policy (only meaningful for MixedMath).
 template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL = 3>
@@ -542,15 +593,21 @@ __host__ __device__ inline void pair_core(const KArgs &K, const M &math, double 
     S I = 0.0, GX = 0.0, GY = 0.0;
     // the vertex registers rotate, so that the loop body is the same for every edge
     S x0 = ax[0], y0 = ay[0], x1 = ax[1], y1 = ay[1], x2 = ax[2], y2 = ay[2];
+    S q0 = x0 * x0 + y0 * y0, q1 = x1 * x1 + y1 * y1, q2 = x2 * x2 + y2 * y2;   // squared radii
+    int skipped = 0;
 #pragma unroll EDGE_UNROLL
     for (int e = 0; e < 3; ++e) {
-        const S xa = x0, ya0 = y0, xb = x1, yb0 = y1;
+        const S xa = x0, ya0 = y0, xb = x1, yb0 = y1, ra2 = q0, rb2 = q1;
         {
-            const S rx = x0, ry = y0;
+            const S rx = x0, ry = y0, rq = q0;
             x0 = x1; y0 = y1; x1 = x2; y1 = y2; x2 = rx; y2 = ry;
+            q0 = q1; q1 = q2; q2 = rq;
         }
         S p, nx, ny, ya, yb;
-        if (!edge_frame(math, xa, ya0, xb, yb0, p, nx, ny, ya, yb)) continue;
+        if (!edge_frame(math, xa, ya0, xb, yb0, p, nx, ny, ya, yb)) {
+            skipped |= 1 << e;
+            continue;
+        }
         // harmonics in the edge frame: theta = psi + phi, (cos phi, sin phi) = n
         S cph[4], sph[4];
         edge_phases(nx, ny, cph, sph);
@@ -568,10 +625,20 @@ __host__ __device__ inline void pair_core(const KArgs &K, const M &math, double 
         sk.hv = hl;
         sk.I = sk.X = sk.Y = 0.0;
         const auto em = math.for_edge(p, tau);
-        for (int pc = 0; pc < K.npieces; ++pc) edge_piece<DEG, ORDER, S>(K, em, pc, p, ya, yb, sk);
+        for (int pc = 0; pc < K.npieces; ++pc) edge_piece<DEG, ORDER, S>(K, em, pc, p, ya, yb, ra2, rb2, sk);
         I += sk.I;
         GX += sk.X * nx - sk.Y * ny;
         GY += sk.X * ny + sk.Y * nx;
+    }
+    // an edge skipped (particle on its line, or zero length) leaves the ray
+    // terms of its neighbours at its two vertices without partners
+    if (skipped) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            // vertex v starts edge v and ends edge v-1
+            const bool out = skipped & (1 << v), in = skipped & (1 << (v == 0 ? 2 : v - 1));
+            if (out != in) vertex_ray_terms<ORDER, S>(K, math, hg, ax[v], ay[v], out ? 1.0 : -1.0, I, GX, GY);
+        }
     }
     const double sg = area2 > 0.0 ? K.cd : -K.cd;
     oI = sg * I;
@@ -610,6 +677,61 @@ __host__ __device__ inline void taylor_shift_T(const S *g, S sx, S sy, S *ge) {
         }
 }
 
+// Transpose of vertex_ray_terms with respect to the global harmonics:
+// adds cI dI/dhg - (1/h) (cX dGX/dhg + cY dGY/dhg) to the weights dg.
+template <int ORDER>
+__device__ inline void vertex_ray_dual(const KArgs &K, double vx, double vy, double s, double invh, double cI,
+                                       double cX, double cY, Harm<double> *dg) {
+    using S = double;
+    const S r2 = vx * vx + vy * vy;
+    if (!(r2 > 0.0)) return;
+    const S ir = rsqrt_nr(r2);
+    const S c1 = vx * ir, s1 = vy * ir;
+    Harm<S> f;                                      // c: sin(n theta)/n, s: -cos(n theta)/n
+    {
+        S cn1 = 1.0, sn1 = 0.0, cn = c1, sn = s1;
+        f.c[0] = f.s[0] = 0.0;
+#pragma unroll
+        for (int n = 1; n <= ORDER + 1; ++n) {
+            const double inv = lit(1.0 / n);
+            f.c[n] = sn * inv;
+            f.s[n] = -cn * inv;
+            const S cn2 = 2.0 * c1 * cn - cn1, sn2 = 2.0 * c1 * sn - sn1;
+            cn1 = cn; sn1 = sn; cn = cn2; sn = sn2;
+        }
+#pragma unroll
+        for (int n = ORDER + 2; n < 5; ++n) f.c[n] = f.s[n] = 0.0;
+    }
+    for (int pc = 0; pc < K.npieces; ++pc) {
+        if (!(r2 > K.R[pc] * K.R[pc])) continue;
+#pragma unroll
+        for (int m = 0; m <= ORDER; ++m) {
+            const double wv = s * cI * K.sv[pc][m];
+            const double wx = -s * invh * cX * K.sw[pc][m], wy = -s * invh * cY * K.sw[pc][m];
+            Harm<S> gx, gy, d;
+#pragma unroll
+            for (int n = 0; n < 5; ++n) {
+                gx.c[n] = wx * f.c[n];
+                gx.s[n] = wx * f.s[n];
+                gy.c[n] = wy * f.c[n];
+                gy.s[n] = wy * f.s[n];
+                d.c[n] = wv * f.c[n];
+                d.s[n] = wv * f.s[n];
+            }
+            // the value part uses only the slots n >= 1 of A_m itself
+            d.c[0] = d.s[0] = 0.0;
+            // the gradient part uses the slots n >= 1 of A_m cos, A_m sin
+            gx.c[0] = gx.s[0] = gy.c[0] = gy.s[0] = 0.0;
+            mul_cs_T(m, gx, gy, d);
+#pragma unroll
+            for (int n = m & 1; n <= m; n += 2) {
+                dg[m].c[n] += d.c[n];
+                dg[m].s[n] += d.s[n];
+            }
+        }
+    }
+}
+
 // Moments mom[k] = int_T xi^k Phi dxi (record order of the monomials about the
 // particle, xi in units of h, with the c_d and 1/h factors of pair_core) of the
 // cotangent-weighted kernel Phi = cI W + cX dW/dx_p + cY dW/dy_p; that is,
@@ -629,15 +751,21 @@ __device__ inline void pair_dual(const KArgs &K, const double *ax, const double 
 #pragma unroll
         for (int n = 0; n < 5; ++n) dg[m].c[n] = dg[m].s[n] = 0.0;
     S x0 = ax[0], y0 = ay[0], x1 = ax[1], y1 = ay[1], x2 = ax[2], y2 = ay[2];
+    S q0 = x0 * x0 + y0 * y0, q1 = x1 * x1 + y1 * y1, q2 = x2 * x2 + y2 * y2;   // squared radii
+    int skipped = 0;
 #pragma unroll EDGE_UNROLL
     for (int e = 0; e < 3; ++e) {
-        const S xa = x0, ya0 = y0, xb = x1, yb0 = y1;
+        const S xa = x0, ya0 = y0, xb = x1, yb0 = y1, ra2 = q0, rb2 = q1;
         {
-            const S rx = x0, ry = y0;
+            const S rx = x0, ry = y0, rq = q0;
             x0 = x1; y0 = y1; x1 = x2; y1 = y2; x2 = rx; y2 = ry;
+            q0 = q1; q1 = q2; q2 = rq;
         }
         S p, nx, ny, ya, yb;
-        if (!edge_frame(math, xa, ya0, xb, yb0, p, nx, ny, ya, yb)) continue;
+        if (!edge_frame(math, xa, ya0, xb, yb0, p, nx, ny, ya, yb)) {
+            skipped |= 1 << e;
+            continue;
+        }
         BasisSink<ORDER, S> sk;
 #pragma unroll
         for (int m = 0; m <= ORDER; ++m)
@@ -647,7 +775,7 @@ __device__ inline void pair_dual(const KArgs &K, const double *ax, const double 
         // coefficient a scalar load from the argument block
 #pragma unroll
         for (int pc = 0; pc < 2; ++pc)
-            if (pc < K.npieces) edge_piece<DEG, ORDER, S>(K, math, pc, p, ya, yb, sk);
+            if (pc < K.npieces) edge_piece<DEG, ORDER, S>(K, math, pc, p, ya, yb, ra2, rb2, sk);
         // the edge's share of cI I + cX GX + cY GY in the edge frame:
         // cI eI - (1/h) (gn eX + gt eY), (gn, gt) = cotangent in (n, t)
         const S wX = -invh * (cX * nx + cY * ny), wY = -invh * (cY * nx - cX * ny);
@@ -672,6 +800,15 @@ __device__ inline void pair_dual(const KArgs &K, const double *ax, const double 
                 dg[m].c[n] += d.c[n] * cph[n] - d.s[n] * sph[n];
                 dg[m].s[n] += d.c[n] * sph[n] + d.s[n] * cph[n];
             }
+        }
+    }
+    // ray terms at the vertices of skipped edges (see pair_core), in the
+    // triangle's frame: weights of the global harmonics directly
+    if (skipped) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const bool out = skipped & (1 << v), in = skipped & (1 << (v == 0 ? 2 : v - 1));
+            if (out != in) vertex_ray_dual<ORDER>(K, ax[v], ay[v], out ? 1.0 : -1.0, invh, cI, cX, cY, dg);
         }
     }
     // transpose of global_harmonics, times the orientation sign and c_d

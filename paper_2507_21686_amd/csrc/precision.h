@@ -7,8 +7,8 @@
 // MixedMath runs them on the FP32 hardware units instead:
 //   * sqrt, 1/sqrt and 1/x start from the FP32 estimate and take one Newton
 //     step in FP64, which leaves a relative error near 2e-14;
-//   * for P0 and P1 fields the arctangent and endpoint direction of the
-//     sector parts stay in FP32 (absolute errors near 1e-7).  A sector part is
+//   * for P0 and P1 fields the arctangent of the sector parts stays in FP32
+//     (absolute errors near 1e-7).  A sector part is
 //     the whole radial kernel integral times an angular factor, so its
 //     sensitivity to the angle is of the size of the integrand and the FP32
 //     rounding is not amplified.  For P3 fields the angular factor is
@@ -58,11 +58,11 @@ struct ExactMath {
     __device__ double sqrt_(double x) const { return x > 0.0 ? sqrt_nr(x) : 0.0; }
     __device__ double rsqrt_(double x) const { return rsqrt_nr(x); }
     __device__ double rcp_(double x) const { return 1.0 / x; }
-    // angular terms of one clipped endpoint: 1/sqrt(p^2 + y^2) and the angle
-    // between the endpoint ray and the circle crossing psi_c
-    __device__ void sector_seed(double p, double ay, double yc, double &ir, double &ang) const {
-        ir = rsqrt_nr(p * p + ay * ay);
-        ang = atan2_q1(p * (ay - yc), p * p + ay * yc);     // both arguments >= 0, the second > 0
+    // angle between the ray to a clipped end at |y| = ay and the circle
+    // crossing psi_c (ay >= yc up to rounding, so both arguments are >= 0 up
+    // to rounding and the second is > 0)
+    __device__ double sector_angle(double p, double ay, double yc) const {
+        return atan2_q1(p * (ay - yc), p * p + ay * yc);
     }
     // H_0 = asinh(yB/p) - asinh(yA/p), with asinh(|y|/p) = log((|y| + rho)/p):
     // one quotient and one logarithm whichever signs the ends have
@@ -119,18 +119,9 @@ struct MixedMath {
         const double r = rcp_f32((float)x);
         return fma(r, fma(-x, r, 1.0), r);
     }
-    __device__ void sector_seed(double p, double ay, double yc, double &ir, double &ang) const {
-        if (exact) {
-            ExactMath().sector_seed(p, ay, yc, ir, ang);
-            return;
-        }
-        if (fp64_angles) {
-            ir = rsqrt_(p * p + ay * ay);
-            ang = atan2_q1(p * (ay - yc), p * p + ay * yc);
-            return;
-        }
-        ir = rsq_f32((float)(p * p + ay * ay));
-        ang = atan2f((float)(p * (ay - yc)), (float)(p * p + ay * yc));
+    __device__ double sector_angle(double p, double ay, double yc) const {
+        if (exact || fp64_angles) return ExactMath().sector_angle(p, ay, yc);
+        return atan2f((float)(p * (ay - yc)), (float)(p * p + ay * yc));
     }
     __device__ double h0(double p, double yA, double yB, double rA, double rB) const {
         if (exact) return ExactMath().h0(p, yA, yB, rA, rB);

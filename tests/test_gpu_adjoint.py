@@ -73,6 +73,41 @@ def test_leibniz_particle_gradient_is_G():
         assert float(err.median()) < 1e-12 * scale
 
 
+@pytest.mark.parametrize("kid", [0, 1, 2, 3])
+@pytest.mark.parametrize("order", [0, 1, 3])
+def test_every_instantiation_nodal_and_leibniz(kid, order):
+    """Every compiled adjoint variant (kernel degree x field order): nodal
+    gradients against the oracle's unit-field integrals (exact by linearity),
+    and the particle gradient of sum I against the forward pass's G."""
+    wl = W.covering_workload(n_side=16, nx=2, ny=4, seed=5, kernel=kid, field_order=order)
+    say(f"adjoint instantiation kid={kid} order={order}")
+    (px, py, tri, nod), off_t, idx_t, g, tg = setup(wl, seed=10 + kid)
+    _, _, _, dnod = sb.integrate_backward(wl.kernel, wl.h, px, py, tri, nod, off_t, idx_t, *tg)
+    I, Gx, Gy = sb.integrate(wl.kernel, wl.h, px, py, tri, nod, off_t, idx_t)
+    one, zero = torch.ones_like(px), torch.zeros_like(px)
+    dpx, dpy, _, _ = sb.integrate_backward(wl.kernel, wl.h, px, py, tri, nod, off_t, idx_t, one, zero, zero)
+    torch.cuda.synchronize()
+    dnod = dnod.cpu().numpy()
+    off, idx = off_t.cpu().numpy(), idx_t.cpu().numpy()
+    own = owners(off)
+    ref = np.zeros_like(wl.nodal)
+    for n in range(wl.n_nodes):
+        unit = np.zeros_like(wl.nodal)
+        unit[n] = 1.0
+        _, _, _, pp = oracle.integrate(kid, wl.h, wl.px, wl.py, wl.tri, unit, off, idx, per_pair=True, nthreads=NTH)
+        contrib = g[0][own] * pp[0] + g[1][own] * pp[1] + g[2][own] * pp[2]
+        ref[n] = np.bincount(idx, weights=contrib, minlength=wl.n_triangles)
+    kfac = {0: 141.0, 1: 1109.0, 2: 8704.0, 3: 30.0}[kid]
+    err = np.abs(dnod - ref).max() / np.abs(ref).max()
+    say(f"  nodal scaled error {err:.2e}")
+    assert err <= 1e-13 * kfac
+    scale = float(torch.maximum(torch.abs(Gx), torch.abs(Gy)).max())
+    for d, gg in ((dpx, Gx), (dpy, Gy)):
+        e = float(torch.abs(d - gg).max()) / scale
+        say(f"  leibniz scaled error {e:.2e}")
+        assert e < 5e-10
+
+
 @pytest.mark.parametrize("kid,order", [(0, 0), (1, 3), (3, 1), (2, 3)])
 def test_vjp_against_oracle(kid, order):
     wl = W.covering_workload(n_side=32, nx=4, ny=8, seed=4, kernel=kid, field_order=order)
@@ -129,6 +164,43 @@ def test_vjp_against_oracle(kid, order):
             worst = max(worst, abs(dref[i] - ref) / max(1.0, abs(ref)))
     say(f"  particle grad worst rel err {worst:.2e}")
     assert worst < 3e-7
+
+
+@pytest.mark.parametrize("kid,order", [(0, 3), (3, 1)])
+def test_vjp_nodal_degenerate_geometry(kid, order):
+    """Nodal gradients (exact by linearity) where a fan triangle is skipped:
+    particle at a vertex, on an edge and on an edge's extension."""
+    say(f"adjoint degenerate geometry kid={kid} order={order}")
+    cases = [
+        [0.0, 0.0, 0.5, 0.1, 0.2, 0.6],
+        [-1.5, 0.0, 1.5, 0.0, 0.0, 1.7],
+        [-0.5, 0.0, 1.5, 0.0, 0.0, 0.7],
+        [0.3, 0.0, 1.8, 0.0, 0.9, 0.9],
+        [-1.2, -0.4, 1.4, -0.4, 0.1, 1.3],
+    ]
+    tri = np.array(cases, dtype=np.float64).T.copy()
+    n = tri.shape[1]
+    nn = {0: 1, 1: 3, 3: 10}[order]
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((nn, n))
+    px, py = np.zeros(n), np.zeros(n)
+    off = np.arange(n + 1, dtype=np.int64)
+    idx = np.arange(n, dtype=np.int32)
+    g = [rng.standard_normal(n) for _ in range(3)]
+    dev = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0", dtype=dt)
+    dpx, dpy, dtri, dnod = sb.integrate_backward(kid, 1.0, dev(px), dev(py), dev(tri), dev(A), dev(off, torch.int64),
+                                                 dev(idx, torch.int32), dev(g[0]), dev(g[1]), dev(g[2]))
+    torch.cuda.synchronize()
+    dnod = dnod.cpu().numpy()
+    ref = np.zeros_like(A)
+    for k in range(nn):
+        unit = np.zeros_like(A)
+        unit[k] = 1.0
+        I, X, Y = oracle.integrate(kid, 1.0, px, py, tri, unit, off, idx)
+        ref[k] = g[0] * I + g[1] * X + g[2] * Y
+    err = np.abs(dnod - ref).max() / max(1.0, np.abs(ref).max())
+    say(f"  nodal gradient scaled error {err:.2e}")
+    assert err < 1e-11
 
 
 def test_autograd_function_and_determinism():

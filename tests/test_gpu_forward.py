@@ -208,6 +208,38 @@ def test_forward_edge_cases():
     assert got[0][0] == 0.0 and abs(got[0][1] - 1.0) < 1e-13
 
 
+@pytest.mark.parametrize("kid,order", [(0, 1), (0, 3), (3, 3), (2, 3)])
+def test_forward_degenerate_geometry_fields(kid, order):
+    """Particles on an edge, on an edge's extension and at a vertex skip a fan
+    triangle; the sector terms of the neighbouring edges at its vertices are
+    then added explicitly.  Linear and cubic fields exercise every harmonic."""
+    say(f"forward degenerate geometry kid={kid} order={order}")
+    cases = [
+        [0.0, 0.0, 0.5, 0.1, 0.2, 0.6],          # particle at a vertex (inside the support)
+        [-1.5, 0.0, 1.5, 0.0, 0.0, 1.7],         # particle on an edge, both ends outside
+        [-0.5, 0.0, 1.5, 0.0, 0.0, 0.7],         # on an edge, one end inside
+        [0.3, 0.0, 1.8, 0.0, 0.9, 0.9],          # on an edge's extension
+        [1.3, 0.0, 2.0, 0.0, 1.2, 0.5],          # on the extension, near end outside
+        [-1.2, -0.4, 1.4, -0.4, 0.1, 1.3],       # particle strictly inside, all ends outside
+        [1e-9, -1.4, 1e-9, 1.4, 1.8, 0.0],       # particle 1e-9 from an edge line
+    ]
+    tri = np.array(cases, dtype=np.float64).T.copy()
+    n = tri.shape[1]
+    nn = {0: 1, 1: 3, 3: 10}[order]
+    A = np.random.default_rng(7).standard_normal((nn, n))
+    px = np.zeros(n)
+    py = np.zeros(n)
+    off = np.arange(n + 1, dtype=np.int64)
+    idx = np.arange(n, dtype=np.int32)
+    got = run_gpu(kid, 1.0, px, py, tri, A, off, idx)
+    ref = oracle.integrate(kid, 1.0, px, py, tri, A, off, idx)
+    for k in range(3):
+        scale = max(1.0, np.abs(ref[k]).max())
+        err = np.abs(got[k] - ref[k]).max() / scale
+        say(f"  component {k}: scaled error {err:.2e}")
+        assert err < 1e-11
+
+
 def test_forward_orientation_independent():
     say("orientation")
     n = 500
