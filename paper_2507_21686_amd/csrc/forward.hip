@@ -161,6 +161,171 @@ __global__ __launch_bounds__(256, fwd_waves(DEG, ORDER, MIXED)) void forward_ker
     }
 }
 
+// Sorted variant.  The lanes of a wavefront evaluate different pairs, and an
+// edge whose line misses the support circle skips the triangle part (radial
+// terms and contraction, the costliest part); lanes that skip it idle while
+// the others run it.  Here a wavefront first classifies the pairs of a window
+// of its pair range by the number of such near edges (0-3), sorts them by that
+// count (counting sort in LDS) and rotates each triangle so that its near
+// edges come first; each 64-pair step then runs the triangle part for roughly
+// the same edge slots in every lane.  Results go to LDS by pair and every
+// particle sums its own pairs in pair order, so the result does not depend on
+// the sort and stays deterministic.
+template <int DEG, int ORDER, bool MIXED, int SW>
+__global__ __launch_bounds__(256, fwd_waves(DEG, ORDER, MIXED)) void forward_sorted_kernel(
+    const KArgs K, double tau, double invh, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ tri_idx, const double *__restrict__ rec,
+    double *__restrict__ I, double *__restrict__ Gx, double *__restrict__ Gy, double *__restrict__ per_pair, int64_t P,
+    int64_t T) {
+    __shared__ double s_res[4][SW][3];
+    __shared__ uint16_t s_perm[4][SW];
+    __shared__ uint8_t s_own[4][SW];
+    __shared__ uint8_t s_key[4][SW];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t p0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64;
+    if (p0 >= N) return;                               // whole wavefront
+    const int64_t pid = p0 + lane;
+    const int64_t plast = p0 + 64 < N ? p0 + 64 : N;
+    const int64_t q_end = min(max(off[plast], (int64_t)0), P);
+    const int64_t my_off = pid < N ? min(max(off[pid], (int64_t)0), q_end) : q_end;
+    const int64_t my_end = pid < N ? min(max(off[pid + 1], my_off), q_end) : q_end;
+    const int64_t q_begin = __shfl(my_off, 0);
+    const double Rout = K.R[K.npieces - 1], R2 = Rout * Rout;
+    constexpr int EU = fwd_edge_unroll(DEG, ORDER);
+    double accI = 0.0, accX = 0.0, accY = 0.0;
+    for (int64_t sbase = q_begin; sbase < q_end; sbase += SW) {
+        const int n = (int)min((int64_t)SW, q_end - sbase);
+        // ---- classify: owner lane, number of near edges, rotation
+        uint64_t cnt = 0;                              // this lane's items per count, 16 bits each
+        for (int c0 = 0; c0 < n; c0 += 64) {
+            const int i = c0 + lane;
+            const int64_t qq = sbase + (i < n ? i : n - 1);
+            int lo = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const int64_t om = __shfl(my_off, lo + step < 64 ? lo + step : 63);
+                if (lo + step < 64 && om <= qq) lo += step;
+            }
+            if (i < n) {
+                int near = 0, rot = 0;
+                const int32_t t = tri_idx[sbase + i];
+                if (t >= 0 && t < T) {
+                    const int64_t ip = p0 + lo < N ? p0 + lo : N - 1;
+                    const double *r = rec + (int64_t)t * kRecDoubles;
+                    const double x = px[ip], y = py[ip];
+                    double ax[3], ay[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        ax[k] = (r[2 * k] - x) * invh;
+                        ay[k] = (r[2 * k + 1] - y) * invh;
+                    }
+                    bool nr[3];
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+                        const int f = e == 2 ? 0 : e + 1;
+                        const double Lx = ax[f] - ax[e], Ly = ay[f] - ay[e];
+                        const double l2 = Lx * Lx + Ly * Ly, cr = ax[e] * Ly - ay[e] * Lx;
+                        nr[e] = l2 > 0.0 && cr * cr < R2 * l2;     // the edge line meets the circle
+                    }
+                    near = (int)nr[0] + (int)nr[1] + (int)nr[2];
+                    // start at the near edge (one), after the far edge (two)
+                    rot = near == 1 ? (nr[0] ? 0 : (nr[1] ? 1 : 2)) : near == 2 ? (!nr[0] ? 1 : (!nr[1] ? 2 : 0)) : 0;
+                }
+                s_own[w][i] = (uint8_t)lo;
+                s_key[w][i] = (uint8_t)(near << 2 | rot);
+                cnt += (uint64_t)1 << (16 * near);
+            }
+        }
+        // ---- counting sort by near-edge count, most near edges first
+        uint64_t inc = cnt;                            // inclusive scan over lanes
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t u = __shfl_up(inc, d);
+            if (lane >= d) inc += u;
+        }
+        const uint64_t tot = __shfl(inc, 63);
+        const uint64_t pre = inc - cnt;
+        int start[4];
+        {
+            const int t3 = (int)(tot >> 48 & 0xffff), t2 = (int)(tot >> 32 & 0xffff), t1 = (int)(tot >> 16 & 0xffff);
+            start[3] = 0;
+            start[2] = t3;
+            start[1] = t3 + t2;
+            start[0] = t3 + t2 + t1;
+        }
+        int run[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) run[b] = start[b] + (int)(pre >> (16 * b) & 0xffff);
+        for (int i = lane; i < n; i += 64) {
+            const int b = s_key[w][i] >> 2;
+            int pos = run[0];
+#pragma unroll
+            for (int bb = 1; bb < 4; ++bb)
+                if (b == bb) pos = run[bb];
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb)
+                if (b == bb) run[bb] = pos + 1;
+            s_perm[w][pos] = (uint16_t)i;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // ---- evaluate in sorted order; results by pair
+        for (int c0 = 0; c0 < n; c0 += 64) {
+            const int j = c0 + lane;
+            if (j < n) {
+                const int item = s_perm[w][j];
+                const int64_t q = sbase + item;
+                const int own = s_own[w][item], key = s_key[w][item];
+                const int64_t ip = p0 + own < N ? p0 + own : N - 1;
+                double vI = 0.0, vX = 0.0, vY = 0.0;
+                const int32_t t = tri_idx[q];
+                if (t >= 0 && t < T) {
+                    const double *r = rec + (int64_t)t * kRecDoubles;
+                    if (MIXED)
+                        pair_fwd_rot<DEG, ORDER, double, MixedMath, EU>(K, MixedMath{false, ORDER >= 2}, tau, px[ip],
+                                                                        py[ip], invh, r, key & 3, vI, vX, vY);
+                    else pair_fwd_rot<DEG, ORDER, double, ExactMath, EU>(K, ExactMath(), 0.0, px[ip], py[ip], invh, r,
+                                                                         key & 3, vI, vX, vY);
+                }
+                if (per_pair) {
+                    per_pair[q] = vI;
+                    per_pair[P + q] = vX;
+                    per_pair[2 * P + q] = vY;
+                }
+                s_res[w][item][0] = vI;
+                s_res[w][item][1] = vX;
+                s_res[w][item][2] = vY;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // ---- every particle sums its pairs of this window in pair order
+        {
+            const int64_t lo = my_off > sbase ? my_off : sbase;
+            const int64_t hi = my_end < sbase + n ? my_end : sbase + n;
+            for (int64_t k = lo; k < hi; ++k) {
+                accI += s_res[w][k - sbase][0];
+                accX += s_res[w][k - sbase][1];
+                accY += s_res[w][k - sbase][2];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (pid < N) {
+        I[pid] = accI;
+        Gx[pid] = accX;
+        Gy[pid] = accY;
+    }
+}
+
+// Sorted or plain kernel per instantiation (measured on the covering
+// workload): sorting pays wherever the triangle part is costly (cubic fields,
+// and the kernels with more radial terms); for the degree-5 kernel with
+// constant or linear fields it costs slightly more than it saves.
+__host__ __device__ constexpr bool fwd_sorted(int deg, int order) { return order >= 2 || deg != 5; }
+
 struct FwdArgs {
     double tau, invh;
     int64_t N;
@@ -176,8 +341,14 @@ template <int DEG, int ORDER, bool MIXED>
 void launch_fwd_t(const KArgs &K, const FwdArgs &a, hipStream_t s) {
     const int64_t waves = (a.N + 63) / 64;
     const int64_t blocks = (waves + 3) / 4;
-    hipLaunchKernelGGL((forward_kernel<DEG, ORDER, MIXED>), dim3((unsigned)blocks), dim3(256), 0, s, K, a.tau,
-                       a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair, a.P, a.T);
+    constexpr int SW = ORDER >= 2 ? 512 : 256;     // LDS: 56 or 28 KB per block
+    if (fwd_sorted(DEG, ORDER))
+        hipLaunchKernelGGL((forward_sorted_kernel<DEG, ORDER, MIXED, SW>), dim3((unsigned)blocks), dim3(256), 0, s, K,
+                           a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair, a.P,
+                           a.T);
+    else
+        hipLaunchKernelGGL((forward_kernel<DEG, ORDER, MIXED>), dim3((unsigned)blocks), dim3(256), 0, s, K, a.tau,
+                           a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair, a.P, a.T);
 }
 
 template <int ORDER, bool MIXED>

@@ -580,6 +580,34 @@ __host__ __device__ inline void pair_fwd(const KArgs &K, const M &math, double t
     pair_core<DEG, ORDER, S, M, EDGE_UNROLL>(K, math, tau, ax, ay, area2, c, invh, oI, oX, oY);
 }
 
+// The same with the triangle's vertices taken from rot (0, 1, 2) on: the
+// integrals do not depend on where the edge loop starts, and a common start
+// lets the lanes of a wavefront take the same branches (see the sorted
+// forward kernel).
+template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL = 3>
+__host__ __device__ inline void pair_fwd_rot(const KArgs &K, const M &math, double tau, S x, S y, double invh,
+                                             const S *__restrict__ r, int rot, S &oI, S &oX, S &oY) {
+    oI = oX = oY = 0.0;
+    S ax[3], ay[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        ax[i] = (r[2 * i] - x) * invh;
+        ay[i] = (r[2 * i + 1] - y) * invh;
+    }
+    const S area2 = (ax[1] - ax[0]) * (ay[2] - ay[0]) - (ax[2] - ax[0]) * (ay[1] - ay[0]);
+    if (area2 == 0.0) return;
+    S c[10];
+    taylor_shift<ORDER, S>(r + 6, ax[0], ay[0], c);
+    S bx[3], by[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int j1 = i == 2 ? 0 : i + 1, j2 = i == 0 ? 2 : i - 1;
+        bx[i] = rot == 0 ? ax[i] : (rot == 1 ? ax[j1] : ax[j2]);
+        by[i] = rot == 0 ? ay[i] : (rot == 1 ? ay[j1] : ay[j2]);
+    }
+    pair_core<DEG, ORDER, S, M, EDGE_UNROLL>(K, math, tau, bx, by, area2, c, invh, oI, oX, oY);
+}
+
 // The pair for a field given as a polynomial about the particle:
 // A(x + h xi) = sum c_ij xi_x^i xi_y^j, vertices (ax, ay) in units of h
 // relative to the particle, area2 their doubled signed area (non-zero).
