@@ -220,17 +220,7 @@ __global__ __launch_bounds__(256, fwd_waves(DEG, ORDER, MIXED)) void forward_sor
                         ax[k] = (r[2 * k] - x) * invh;
                         ay[k] = (r[2 * k + 1] - y) * invh;
                     }
-                    bool nr[3];
-#pragma unroll
-                    for (int e = 0; e < 3; ++e) {
-                        const int f = e == 2 ? 0 : e + 1;
-                        const double Lx = ax[f] - ax[e], Ly = ay[f] - ay[e];
-                        const double l2 = Lx * Lx + Ly * Ly, cr = ax[e] * Ly - ay[e] * Lx;
-                        nr[e] = l2 > 0.0 && cr * cr < R2 * l2;     // the edge line meets the circle
-                    }
-                    near = (int)nr[0] + (int)nr[1] + (int)nr[2];
-                    // start at the near edge (one), after the far edge (two)
-                    rot = near == 1 ? (nr[0] ? 0 : (nr[1] ? 1 : 2)) : near == 2 ? (!nr[0] ? 1 : (!nr[1] ? 2 : 0)) : 0;
+                    near = near_edges(ax, ay, R2, rot);
                 }
                 s_own[w][i] = (uint8_t)lo;
                 s_key[w][i] = (uint8_t)(near << 2 | rot);

@@ -580,6 +580,24 @@ __host__ __device__ inline void pair_fwd(const KArgs &K, const M &math, double t
     pair_core<DEG, ORDER, S, M, EDGE_UNROLL>(K, math, tau, ax, ay, area2, c, invh, oI, oX, oY);
 }
 
+// Number of edges whose line meets the circle of radius^2 R2 about the
+// particle (vertices relative to the particle), and the rotation that puts
+// those edges first: the start edge when there is one, the edge after the far
+// one when there are two.
+__host__ __device__ inline int near_edges(const double *ax, const double *ay, double R2, int &rot) {
+    bool nr[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int f = e == 2 ? 0 : e + 1;
+        const double Lx = ax[f] - ax[e], Ly = ay[f] - ay[e];
+        const double l2 = Lx * Lx + Ly * Ly, cr = ax[e] * Ly - ay[e] * Lx;
+        nr[e] = l2 > 0.0 && cr * cr < R2 * l2;
+    }
+    const int near = (int)nr[0] + (int)nr[1] + (int)nr[2];
+    rot = near == 1 ? (nr[0] ? 0 : (nr[1] ? 1 : 2)) : near == 2 ? (!nr[0] ? 1 : (!nr[1] ? 2 : 0)) : 0;
+    return near;
+}
+
 // The same with the triangle's vertices taken from rot (0, 1, 2) on: the
 // integrals do not depend on where the edge loop starts, and a common start
 // lets the lanes of a wavefront take the same branches (see the sorted
