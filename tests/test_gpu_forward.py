@@ -240,6 +240,52 @@ def test_forward_degenerate_geometry_fields(kid, order):
         assert err < 1e-11
 
 
+@pytest.mark.parametrize("kid,order", [(1, 1), (0, 3), (0, 0), (3, 3)])
+def test_forward_dense_pairs_many_windows(kid, order):
+    """About a thousand pairs per particle: a wavefront's pairs span several
+    sorting windows and single particles' pairs are split between windows
+    (and, for the unsorted kernel, between many 64-pair steps)."""
+    say(f"forward dense pairs kid={kid} order={order}")
+    tri = W.covering_mesh(40, 80, seed=3)
+    T = tri.shape[1]
+    rng = np.random.default_rng(kid * 10 + order)
+    n = 70
+    px = rng.uniform(0.2, 0.8, n)
+    py = rng.uniform(0.2, 0.8, n)
+    nn = {0: 1, 1: 3, 3: 10}[order]
+    A = rng.standard_normal((nn, T))
+    h = 0.22
+    tpx, tpy, ttri = to_dev(px, py, tri)
+    toff, tidx = sb.pairlist(tpx, tpy, ttri, h)
+    torch.cuda.synchronize()
+    off, idx = toff.cpu().numpy(), tidx.cpu().numpy()
+    say(f"  pairs {idx.size} ({idx.size / n:.0f} per particle)")
+    assert idx.size / n > 600
+    got = run_gpu(kid, h, px, py, tri, A, off, idx)
+    ref = oracle.integrate(kid, h, px, py, tri, A, off, idx, nthreads=16)
+    # error model of the random-pairs test, summed over each particle's pairs:
+    # 8 eps K kappa per pair, kappa = (d_max/width)^order of the pair (the
+    # triangles are 1/80 wide under a support of 0.22, so kappa reaches ~20
+    # for linear and ~1e4 for cubic fields)
+    own = np.repeat(np.arange(n), np.diff(off))
+    rel = tri[:, idx].copy()
+    rel[0::2] -= px[own]
+    rel[1::2] -= py[own]
+    rel /= h
+    amax = np.maximum(np.abs(A[:, idx]).max(0) * (3.0 if nn == 10 else 1.0), 1.0)
+    per_pair = 8 * 1.1e-16 * KFAC[kid] * conditioning(rel, order) * amax
+    bI = np.bincount(own, weights=per_pair, minlength=n)
+    bG = bI * metrics.grad_scale(kid, h)
+    for k, b in ((0, bI), (1, bG), (2, bG)):
+        r = np.abs(got[k] - ref[k]) / b
+        say(f"  component {k}: worst error / bound {r.max():.2f}, scaled error {np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max():.2e}")
+        assert np.all(r <= 1.0)
+    # deterministic
+    again = run_gpu(kid, h, px, py, tri, A, off, idx)
+    for k in range(3):
+        assert np.array_equal(got[k], again[k])
+
+
 def test_forward_orientation_independent():
     say("orientation")
     n = 500
