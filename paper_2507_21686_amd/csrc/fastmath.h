@@ -73,10 +73,5 @@ __device__ inline double log_pos(double x) {
     return fma(de, sconst(0.6931471803691238), fma(de, sconst(1.9082149292705877e-10), lm));
 }
 
-// generic fallbacks (dual numbers in the adjoint use their own overloads)
-template <typename S>
-__host__ __device__ inline S atan2_q1(const S &y, const S &x) { return atan2(y, x); }
-template <typename S>
-__host__ __device__ inline S log_pos(const S &x) { return log(x); }
 
 }  // namespace sphbi

@@ -1,8 +1,7 @@
-// Closed-form pair mathematics shared by the forward and adjoint kernels.
-// Templated on the scalar type S: double for the forward path, a
-// forward-mode dual number for the adjoint (derivatives with respect to the
-// triangle vertices propagate through every step, including the clipping).
-// See forward.hip for the derivation.
+// Closed-form pair mathematics shared by the forward and adjoint kernels
+// (scalar type S is double throughout; the precision policy M decides how the
+// square roots, reciprocals and angles are evaluated).  See forward.hip for the
+// derivation.
 #pragma once
 
 #include <math.h>

@@ -63,7 +63,7 @@ def test_leibniz_particle_gradient_is_G():
     dpx, dpy, _, _ = sb.integrate_backward(wl.kernel, wl.h, px, py, tri, nod, off, idx, one, zero, zero)
     torch.cuda.synchronize()
     scale = float(torch.maximum(torch.abs(Gx), torch.abs(Gy)).max())
-    # two code paths (dual-number derivative of I vs the closed form of G).
+    # two code paths (the transport-rule derivative of I vs the closed form of G).
     # Wendland C4 (monomial cancellation 1.1e3) with a cubic field extrapolated
     # over particle-anchored pieces of aspect-ratio-20 triangles: the worst
     # particle loses about 1e-10 relative, the typical one 1e-13.
