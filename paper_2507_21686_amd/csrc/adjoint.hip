@@ -392,8 +392,21 @@ __global__ __launch_bounds__(256) void tri_reduce(int64_t T, int n_nodes, const 
     const int k = (int)(g & 15);
     if (t >= T) return;
     double acc = 0.0;
-    if (k < NG)
-        for (int64_t i = start[t]; i < start[t + 1]; ++i) acc += pair_grad[(int64_t)perm[i] * NG + k];
+    if (k < NG) {
+        const int64_t i0 = start[t], i1 = start[t + 1];
+        int64_t i = i0;
+        // four pairs' loads in flight, added in pair order
+        for (; i + 4 <= i1; i += 4) {
+            const int32_t a = perm[i], b = perm[i + 1], c = perm[i + 2], d = perm[i + 3];
+            const double ga = pair_grad[(int64_t)a * NG + k], gb = pair_grad[(int64_t)b * NG + k];
+            const double gc = pair_grad[(int64_t)c * NG + k], gd = pair_grad[(int64_t)d * NG + k];
+            acc += ga;
+            acc += gb;
+            acc += gc;
+            acc += gd;
+        }
+        for (; i < i1; ++i) acc += pair_grad[(int64_t)perm[i] * NG + k];
+    }
     if (k < 6) dtri[k * T + t] = acc;
     else if (k < 6 + n_nodes) dnodal[(k - 6) * T + t] = acc;
 }
