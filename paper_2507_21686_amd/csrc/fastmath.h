@@ -18,10 +18,20 @@ namespace sphbi {
 // inside the polynomial.  sconst() hands the constant over through an opaque
 // scalar-register operand at the point of use, so it costs two scalar moves
 // (issued beside the vector work) and no vector register.
+//
+// A translation unit that defines SPHBI_PLAIN_CONSTANTS before including this
+// header gets plain constants instead.  The adjoint does: its kernels run one
+// wave per SIMD whatever the constants cost, and in its largest fully
+// unrolled instantiations (cubic field) the opaque operand came out of the
+// compiler with wrong results, which plain constants do not.
+#ifdef SPHBI_PLAIN_CONSTANTS
+__device__ inline double sconst(double c) { return c; }
+#else
 __device__ inline double sconst(double c) {
     asm volatile("" : "+s"(c));
     return c;
 }
+#endif
 
 // atan(y / x) for y >= 0, x > 0.  After swapping so that the ratio is at
 // most 1, the identity atan(t) = pi/4 + atan((t - 1)/(t + 1)) brings it to

@@ -52,5 +52,10 @@ int launch_backward(int order, int deg, const KArgs &K, double h, int64_t N, con
                     const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,
                     const double *nodal, const double *gI, const double *gX, const double *gY, double *dpx,
                     double *dpy, double *dtri, double *dnodal, void *ws, hipStream_t s);
+// the adjoint pair kernel for linear fields (its own translation unit)
+void launch_adjoint_linear(int deg, const KArgs &K, double invh, int64_t N, const double *px, const double *py,
+                           const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,
+                           const double *nodal, const double *gI, const double *gX, const double *gY, double *dpx,
+                           double *dpy, double *pair_grad, hipStream_t s);
 
 }  // namespace sphbi

@@ -260,11 +260,19 @@ __host__ __device__ inline void taylor_shift(const S *__restrict__ e, S sx, S sy
 // (value harmonics n = m, m-2, ... and gradient harmonics n = m+1, m-1, ...
 // of the degree-m part of the field).
 //
+// A sink may also take the radial terms themselves (radial(), after they are
+// formed): kHMax, kPMax are the largest indices of H and P it reads beyond the
+// contraction's, and kOnLine says the edge may lie on a line through the
+// particle (p = 0), where H_0 is taken as 0 (it only ever appears times p).
+//
 // FieldSink contracts them with one field's edge-frame harmonics hv and adds
 // the value and gradient integrals (without c_d and the -1/h of the
 // gradient).
 template <typename S>
 struct FieldSink {
+    static constexpr int kHMax = 0, kPMax = 0;
+    static constexpr bool kOnLine = false;
+    __host__ __device__ void radial(const KArgs &, int, S, const S *, const S *) {}
     const Harm<S> *hv;
     S I, X, Y;
     Harm<S> hx, hy;
@@ -294,6 +302,9 @@ struct FieldSink {
 // monomials at the cost of one evaluation).
 template <int ORDER, typename S>
 struct BasisSink {
+    static constexpr int kHMax = 0, kPMax = 0;
+    static constexpr bool kOnLine = false;
+    __host__ __device__ void radial(const KArgs &, int, S, const S *, const S *) {}
     Harm<S> vb[ORDER + 1], gb[ORDER + 1];
     __host__ __device__ void sector(int m, double sv, double sw, const S *angc, const S *angs) {
 #pragma unroll
@@ -318,6 +329,164 @@ struct BasisSink {
     }
 };
 
+// Boundary line integrals of the adjoint: the transport term of an edge that
+// moves with its vertices.  For the edge from a to b, t = (y - ya)/(yb - ya),
+//   Ja = int (1 - t) A Phi ds,   Jb = int t A Phi ds,
+// Phi = cI W + cX dW/dx_p + cY dW/dy_p, taken over the part of the edge inside
+// the support.  On the edge line (distance p, coordinate y, rho^2 = p^2 + y^2)
+// the integrand is a polynomial in y times W(rho) or W'(rho)/rho, and with
+// y^a = y^(a mod 2) (rho^2 - p^2)^(a div 2) every term reduces to the radial
+// terms of edge_piece, H_c = int rho^(c-1) dy and P_e = int y rho^(e-1) dy.
+// add() folds in the kernel piece by piece (the pieces share p):
+//   G0[i] = sum_j b_j H_(2i+j+1),    G1[i] = sum_j b_j P_(2i+j+1),
+//   K0[i] = sum_j j b_j H_(2i+j-1),  K1[i] = sum_j j b_j P_(2i+j-1),
+// and finish() expands, with m = a div 2,
+//   int y^a W dy              = sum_i C(m,i) (-p^2)^(m-i) (a even ? G0 : G1)[i],
+//   h int y^a W'(rho)/rho dy  = the same with K0, K1,
+// and contracts them with the field along the line.
+template <int DEG, int ORDER, typename S>
+struct LineSums {
+    static constexpr int NP = ORDER + 2;          // t A has degree ORDER + 1
+    static constexpr int NQ = ORDER + 3;          // t A (p gn + y gt) has degree ORDER + 2
+    static constexpr int NG0 = (NP + 1) / 2, NG1 = NP / 2, NK0 = (NQ + 1) / 2, NK1 = NQ / 2;
+    static constexpr int kHMax = DEG + 2 * NG0 - 1 > DEG + 2 * NK0 - 3 ? DEG + 2 * NG0 - 1 : DEG + 2 * NK0 - 3;
+    static constexpr int kPMax = DEG + 2 * NG1 - 1 > DEG + 2 * NK1 - 3 ? DEG + 2 * NG1 - 1 : DEG + 2 * NK1 - 3;
+    S G0[NG0], G1[NG1], K0[NK0], K1[NK1];
+    __device__ void clear() {
+#pragma unroll
+        for (int i = 0; i < NG0; ++i) G0[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < NG1; ++i) G1[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < NK0; ++i) K0[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < NK1; ++i) K1[i] = 0.0;
+    }
+    // the radial terms of piece pc, from ya to yb (either direction)
+    __device__ void add(const KArgs &K, int pc, const S *H, const S *P) {
+#pragma unroll
+        for (int j = 0; j <= DEG; ++j) {
+            const double bj = K.b[pc][j];
+#pragma unroll
+            for (int i = 0; i < NG0; ++i) G0[i] = fma(bj, H[2 * i + j + 1], G0[i]);
+#pragma unroll
+            for (int i = 0; i < NG1; ++i) G1[i] = fma(bj, P[2 * i + j + 1], G1[i]);
+            if (j >= 1) {
+                const double kb = lit(j) * bj;
+#pragma unroll
+                for (int i = 0; i < NK0; ++i) K0[i] = fma(kb, H[2 * i + j - 1], K0[i]);
+#pragma unroll
+                for (int i = 0; i < NK1; ++i) K1[i] = fma(kb, P[2 * i + j - 1], K1[i]);
+            }
+        }
+    }
+    // Ja, Jb (world units, c_d and the 1/h of the gradient included) for the
+    // edge from ya to yb on the line p n + y tau, tau = (-ny, nx); c is the
+    // field about the particle in units of h, record order
+    __device__ void finish(S p, S ya, S yb, S nx, S ny, const S *c, double cI, double cX, double cY, double invh,
+                           double cd, S &Ja, S &Jb) const {
+        // A along the line: xi_x = p nx - y ny, xi_y = p ny + y nx
+        S X[ORDER + 1][ORDER + 1], Y[ORDER + 1][ORDER + 1];     // coefficients of xi_x^i, xi_y^i in y
+#pragma unroll
+        for (int i = 0; i <= ORDER; ++i)
+#pragma unroll
+            for (int q = 0; q <= ORDER; ++q) X[i][q] = Y[i][q] = 0.0;
+        X[0][0] = Y[0][0] = 1.0;
+#pragma unroll
+        for (int i = 1; i <= ORDER; ++i)
+#pragma unroll
+            for (int q = 0; q <= i; ++q) {
+                X[i][q] = p * nx * X[i - 1][q] + (q > 0 ? S(-ny * X[i - 1][q - 1]) : S(0.0));
+                Y[i][q] = p * ny * Y[i - 1][q] + (q > 0 ? S(nx * Y[i - 1][q - 1]) : S(0.0));
+            }
+        S Ay[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) Ay[q] = 0.0;
+#pragma unroll
+        for (int m = 0; m <= ORDER; ++m)
+#pragma unroll
+            for (int j = 0; j <= m; ++j) {
+                const int i = m - j;
+                const S cij = c[pidx(i, j)];
+#pragma unroll
+                for (int qa = 0; qa <= i; ++qa)
+#pragma unroll
+                    for (int qb = 0; qb <= j; ++qb) Ay[qa + qb] += cij * X[i][qa] * Y[j][qb];
+            }
+        // Pb = t A, Pa = A - Pb
+        const S il = 1.0 / (yb - ya);
+        S Pa[NP], Pb[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const S prev = q > 0 ? Ay[q - 1] : S(0.0);
+            Pb[q] = il * (prev - ya * Ay[q]);
+            Pa[q] = Ay[q] - Pb[q];
+        }
+        // int y^a W dy (U) and h int y^a W'/rho dy (V)
+        const S p2 = p * p;
+        auto expand = [&](int a, const S *g0, const S *g1) -> S {
+            const int m = a >> 1;
+            S s = 0.0, pw = 1.0;
+#pragma unroll
+            for (int i = 2; i >= 0; --i) {
+                if (i > m) continue;
+                const S gi = (a & 1) ? g1[i] : g0[i];
+                const double w = (m == 2 && i == 1) ? 2.0 : 1.0;     // C(m, i), m <= 2
+                s = fma(w == 1.0 ? pw : S(lit(w) * pw), gi, s);
+                pw *= -p2;
+            }
+            return s;
+        };
+        S s1a = 0.0, s1b = 0.0, s2a = 0.0, s2b = 0.0;
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+            const S u = expand(a, G0, G1);
+            s1a = fma(Pa[a], u, s1a);
+            s1b = fma(Pb[a], u, s1b);
+        }
+        // cX xi_x + cY xi_y = p gn + y gt along the line
+        const S gn = cX * nx + cY * ny, gt = cY * nx - cX * ny;
+        const S pg = p * gn;
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) {
+            const S v = expand(a, K0, K1);
+            S qa = a < NP ? S(pg * Pa[a]) : S(0.0), qb = a < NP ? S(pg * Pb[a]) : S(0.0);
+            if (a > 0) {
+                qa = fma(gt, Pa[a - 1], qa);
+                qb = fma(gt, Pb[a - 1], qb);
+            }
+            s2a = fma(qa, v, s2a);
+            s2b = fma(qb, v, s2b);
+        }
+        // the radial terms ran from ya to yb
+        const S f = yb > ya ? S(cd * invh) : S(-cd * invh);
+        Ja = f * (cI * s1a - invh * s2a);
+        Jb = f * (cI * s1b - invh * s2b);
+    }
+};
+
+// BasisSink that also collects the line sums of the same edge.
+template <int DEG, int ORDER, typename S>
+struct BasisLineSink : BasisSink<ORDER, S> {
+    static constexpr int kHMax = LineSums<DEG, ORDER, S>::kHMax, kPMax = LineSums<DEG, ORDER, S>::kPMax;
+    LineSums<DEG, ORDER, S> ln;
+    __device__ void radial(const KArgs &K, int pc, S, const S *H, const S *P) { ln.add(K, pc, H, P); }
+};
+
+// The line sums alone, for an edge on a line through the particle: it has no
+// fan triangle, but its line integral remains.
+template <int DEG, int ORDER, typename S>
+struct LineSink {
+    static constexpr int kHMax = LineSums<DEG, ORDER, S>::kHMax, kPMax = LineSums<DEG, ORDER, S>::kPMax;
+    static constexpr bool kOnLine = true;
+    LineSums<DEG, ORDER, S> ln;
+    __device__ void radial(const KArgs &K, int pc, S, const S *H, const S *P) { ln.add(K, pc, H, P); }
+    __device__ void sector(int, double, double, const S *, const S *) {}
+    __device__ void begin(int) {}
+    __device__ void value(int, int, S, S) {}
+    __device__ void grad(int, int, S, S) {}
+};
+
 // One edge of the signed fan, one kernel piece of radius R, handed to a sink.
 // ra2, rb2 are the squared distances of the edge's ends from the particle: an
 // end is clipped (outside the circle) by the same test in both edges that
@@ -325,8 +494,8 @@ struct BasisSink {
 template <int DEG, int ORDER, typename S, typename M, typename Sink>
 __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc, S p, S ya, S yb, S ra2, S rb2,
                                            Sink &sink) {
-    constexpr int HMAX = DEG + ORDER + 1;
-    constexpr int PMAX = DEG + ORDER;
+    constexpr int HMAX = DEG + ORDER + 1 > Sink::kHMax ? DEG + ORDER + 1 : Sink::kHMax;
+    constexpr int PMAX = DEG + ORDER > Sink::kPMax ? DEG + ORDER : Sink::kPMax;
     const double R = K.R[pc];
     const S yc = p < R ? S(math.sqrt_((R - p) * (R + p))) : S(0.0);
     const S aya = fabs(ya), ayb = fabs(yb);
@@ -383,7 +552,7 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
         // H_0 = asinh(yB/p) - asinh(yA/p) with a single logarithm
         const S h0 = math.h0(p, yA, yB, rA, rB);
         const S p2 = p * p;
-        H[0] = h0;
+        H[0] = Sink::kOnLine && !(p > 0.0) ? S(0.0) : h0;
         H[1] = yB - yA;
         S gA = 1.0, gB = 1.0;          // rho^{c-1}
 #pragma unroll
@@ -400,6 +569,8 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
             qB *= rB;
         }
     }
+    sink.radial(K, pc, p, H, P);
+    if constexpr (Sink::kOnLine) return;
     S pj[ORDER + 3];
     pj[0] = p;                             // p^{j+1}
 #pragma unroll
@@ -785,11 +956,28 @@ __device__ inline void vertex_ray_dual(const KArgs &K, double vx, double vy, dou
 // edge, the closed-form integrals of every harmonic slot (BasisSink), weights
 // them with the cotangents, and carries the weights back through the product
 // with (cos, sin), the edge rotation and the monomial-to-harmonic map.
+//
+// The same radial terms give the boundary line integrals of the transport
+// term (LineSums): gv[2k], gv[2k+1] receive the line part of the gradient with
+// respect to vertex k (world units), for the field c about the particle
+// (units of h, record order).
 template <int DEG, int ORDER, int EDGE_UNROLL = 3>
 __device__ inline void pair_dual(const KArgs &K, const double *ax, const double *ay, double area2, double invh,
-                                 double cI, double cX, double cY, double *mom) {
+                                 double cI, double cX, double cY, const double *c, double *mom, double *gv) {
     using S = double;
     const ExactMath math;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gv[k] = 0.0;
+    // adds the line integrals of edge e (vertex e to e+1) times the outward normal
+    auto add_line = [&](int e, S Ja, S Jb, S ox, S oy) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const S w = k == e ? Ja : (k == (e == 2 ? 0 : e + 1) ? Jb : S(0.0));
+            gv[2 * k] = fma(w, ox, gv[2 * k]);
+            gv[2 * k + 1] = fma(w, oy, gv[2 * k + 1]);
+        }
+    };
+    const double so = area2 > 0.0 ? 1.0 : -1.0;
     Harm<S> dg[ORDER + 1];          // weights of the global-frame harmonics
 #pragma unroll
     for (int m = 0; m <= ORDER; ++m)
@@ -809,9 +997,28 @@ __device__ inline void pair_dual(const KArgs &K, const double *ax, const double 
         S p, nx, ny, ya, yb;
         if (!edge_frame(math, xa, ya0, xb, yb0, p, nx, ny, ya, yb)) {
             skipped |= 1 << e;
+            const S Lx = xb - xa, Ly = yb0 - ya0;
+            const S len2 = Lx * Lx + Ly * Ly;
+            if (len2 != 0.0) {
+                // the edge lies on a line through the particle: y along the
+                // edge (tau = t, normal (ty, -tx))
+                S len, il;
+                math.edge_norm(len2, len, il);
+                const S tx = Lx * il, ty = Ly * il;
+                const S la = xa * tx + ya0 * ty, lb = la + len;
+                LineSink<DEG, ORDER, S> ls;
+                ls.ln.clear();
+#pragma unroll
+                for (int pc = 0; pc < 2; ++pc)
+                    if (pc < K.npieces) edge_piece<DEG, ORDER, S>(K, math, pc, S(0.0), la, lb, ra2, rb2, ls);
+                S Ja, Jb;
+                ls.ln.finish(S(0.0), la, lb, ty, -tx, c, cI, cX, cY, invh, K.cd, Ja, Jb);
+                add_line(e, Ja, Jb, so * ty, -so * tx);
+            }
             continue;
         }
-        BasisSink<ORDER, S> sk;
+        BasisLineSink<DEG, ORDER, S> sk;
+        sk.ln.clear();
 #pragma unroll
         for (int m = 0; m <= ORDER; ++m)
 #pragma unroll
@@ -845,6 +1052,14 @@ __device__ inline void pair_dual(const KArgs &K, const double *ax, const double 
                 dg[m].c[n] += d.c[n] * cph[n] - d.s[n] * sph[n];
                 dg[m].s[n] += d.c[n] * sph[n] + d.s[n] * cph[n];
             }
+        }
+        // line integrals; the outward normal (ty, -tx) so, with (ty, -tx) =
+        // +-(nx, ny) as yb > ya or not
+        {
+            S Ja, Jb;
+            sk.ln.finish(p, ya, yb, nx, ny, c, cI, cX, cY, invh, K.cd, Ja, Jb);
+            const S o = (yb > ya) == (area2 > 0.0) ? 1.0 : -1.0;
+            add_line(e, Ja, Jb, o * nx, o * ny);
         }
     }
     // ray terms at the vertices of skipped edges (see pair_core), in the
