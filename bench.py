@@ -173,6 +173,32 @@ def bench_adjoint(args, sb, W, torch, dev):
                         f"gradients for positions, vertices and nodal values (FP64)"}
 
 
+def bench_operators(args, sb, torch, dev, wl, px, py, tri, nodal, off, idx, fwd_ms):
+    """SPH operators (Sec. 2) on the headline workload: difference gradient
+    (per-pair pre-weights), divergence and curl (two fields, one pass) and the
+    boundary normal, each against the forward pair kernel on the same pairs."""
+    P, N = int(idx.numel()), wl.n_particles
+    g = torch.Generator(device=dev).manual_seed(5)
+    rho = 1000.0 + 100.0 * torch.rand(nodal.shape, dtype=torch.float64, device=dev, generator=g)
+    ay = torch.randn(nodal.shape, dtype=torch.float64, device=dev, generator=g)
+    ap = torch.randn(N, dtype=torch.float64, device=dev, generator=g)
+    rp = 1000.0 + 100.0 * torch.rand(N, dtype=torch.float64, device=dev, generator=g)
+    steps = max(3, args.steps // 2)
+    out = {}
+    cases = (("difference_gradient", lambda: sb.gradient_difference(wl.kernel, wl.h, px, py, ap, rp, tri, nodal, rho,
+                                                                    off, idx)),
+             ("symmetric_gradient", lambda: sb.gradient_symmetric(wl.kernel, wl.h, px, py, ap, rp, tri, nodal, rho,
+                                                                  off, idx)),
+             ("divergence_curl", lambda: sb.divergence_curl(wl.kernel, wl.h, px, py, tri, nodal, ay, off, idx)),
+             ("boundary_normal", lambda: sb.boundary_normal(wl.kernel, wl.h, px, py, tri, off, idx)))
+    for name, fn in cases:
+        ms = event_time(torch, fn, steps, 2)
+        out[name] = {"ms": ms, "pairs_per_s": P / (ms * 1e-3), "over_forward_kernel": ms / fwd_ms}
+        log(f"bench: operator {name} {ms:.3f} ms ({P / (ms * 1e-3):.3e} pairs/s, {ms / fwd_ms:.2f}x forward kernel)")
+    out["workload"] = "the headline workload's pairs; P3 fields, Wendland C2, FP64"
+    return out
+
+
 def bench_surrogate(args, sb, torch, dev):
     """Train the surrogate (Wendland C2, unit P0 field) on the GPU with the
     library's kernels, calibrate its router on a held-out mesh and time the
@@ -252,6 +278,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the surrogate")
+    ap.add_argument("--no-operators", action="store_true", help="skip timing the SPH operators")
     ap.add_argument("--surrogate-steps", type=int, default=40000, help="Adam steps of the surrogate training")
     ap.add_argument("--surrogate-level", type=float, default=1e-2,
                     help="scale-normalised per-pair error the router is calibrated to")
@@ -379,6 +406,9 @@ def main():
         },
     }
 
+    if not args.no_operators:
+        result["modes"]["operators"] = bench_operators(args, sb, torch, dev, wl, px, py, tri, nodal, off, idx,
+                                                       kern_avg)
     if not args.no_adjoint:
         result["modes"]["adjoint"] = bench_adjoint(args, sb, W, torch, dev)
     if not args.no_surrogate:

@@ -189,6 +189,44 @@ int sphbi_integrate_backward(const sphbi_kernel *kernel /* host */, const sphbi_
                              double *dpy, double *dtri, double *dnodal, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------
+ * SPH operators on the boundary (Sec. 2) and the boundary normal (App. A).
+ *
+ * One call evaluates, for every particle x, op applied to boundary fields
+ * given by nodal values on the triangles ([n_nodes][T], the layout of
+ * sphbi_integrate), summed over the particle's pairs:
+ *
+ *   SPHBI_OP_GRAD_DIFFERENCE  (out_a, out_b) = difference gradient of A
+ *       (eq. sphdiffops, first form; continuous form eq. intsphdiffops):
+ *       (1/rho(x)) int f grad W, f interpolated from the pre-weights
+ *       f_i = rho_i (A_i - A(x)) at the element's nodes.
+ *       fa = A, fb = rho (nodal); qa = A(x), qb = rho(x) [N].
+ *   SPHBI_OP_GRAD_SYMMETRIC   (out_a, out_b) = symmetric gradient of A:
+ *       rho(x) int f grad W, f_i = rho_i (A_i / rho_i^2 + A(x) / rho(x)^2)
+ *       (the sign of the pre-weights given with eq. improper and used in
+ *       App. A for the pressure term).  Same arguments.
+ *   SPHBI_OP_DIV_CURL         out_a = divergence, out_b = curl of the vector
+ *       field (A_x, A_y): <grad A_x>_x + <grad A_y>_y and
+ *       <grad A_y>_x - <grad A_x>_y.  fa = A_x, fb = A_y; qa, qb unused.
+ *   SPHBI_OP_NORMAL           (out_a, out_b) = int grad W (the unit field;
+ *       App. A).  n_nodes, fa, fb, qa, qb unused.
+ *
+ * "grad" is with respect to the particle position (as G of
+ * sphbi_integrate, 1/h included).  Densities must be non-zero.  Pair list,
+ * kernel and h as in sphbi_integrate.  FP64 only (opts may be NULL; MIXED
+ * is rejected with SPHBI_EUNSUPPORTED).  No workspace.  Asynchronous.
+ * ------------------------------------------------------------------- */
+#define SPHBI_OP_GRAD_DIFFERENCE 0
+#define SPHBI_OP_GRAD_SYMMETRIC 1
+#define SPHBI_OP_DIV_CURL 2
+#define SPHBI_OP_NORMAL 3
+
+int sphbi_operator(const sphbi_kernel *kernel /* host */, const sphbi_opts *opts /* host, NULL = default */,
+                   int32_t op, double h, int32_t n_nodes, int64_t N, const double *px, const double *py,
+                   const double *qa, const double *qb, int64_t T, const double *tri, const double *fa,
+                   const double *fb, const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, double *out_a,
+                   double *out_b, void *stream);
+
+/* ---------------------------------------------------------------------
  * Learned surrogate of the per-pair result (an extension; the paper has no
  * learned part).  A network 8 -> 128 -> 128 -> 128 -> 4 maps the
  * canonical features of a pair to the standardised (I, h Gx, h Gy) of a unit

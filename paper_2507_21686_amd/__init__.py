@@ -80,6 +80,8 @@ def lib():
         L.sphbi_integrate_backward.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, i32, i64, vp, vp,
                                                i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp,
                                                C.c_size_t, vp]
+        L.sphbi_operator.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), i32, d, i32, i64, vp, vp, vp,
+                                     vp, i64, vp, vp, vp, vp, vp, i64, vp, vp, vp]
         f = C.c_float
         L.sphbi_surrogate_features.argtypes = [d, i64, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
         L.sphbi_surrogate_targets.argtypes = [i64, d, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
@@ -269,6 +271,62 @@ def integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx, per_pair=False, p
     """Per-particle (I, Gx, Gy) [N] (and optionally per-pair [3, P]) on the GPU."""
     return Integrator(kernel, h, nodal.shape[0], precision, tau_edge)(px, py, tri, nodal, offsets, tri_idx,
                                                                       per_pair=per_pair)
+
+
+# ----------------------------------------------------------------------------
+# SPH operators on the boundary (Sec. 2) and the boundary normal (App. A)
+# ----------------------------------------------------------------------------
+OP_GRAD_DIFFERENCE, OP_GRAD_SYMMETRIC, OP_DIV_CURL, OP_NORMAL = 0, 1, 2, 3
+
+
+def operator(op, kernel, h, px, py, tri, offsets, tri_idx, fa=None, fb=None, qa=None, qb=None):
+    """``sphbi_operator``: two per-particle outputs [N] of operator ``op``.
+
+    OP_GRAD_DIFFERENCE / OP_GRAD_SYMMETRIC: fa = A, fb = rho nodal [n_nodes, T],
+    qa = A(x), qb = rho(x) [N] -> (d/dx, d/dy); OP_DIV_CURL: fa = A_x, fb = A_y
+    -> (div, curl); OP_NORMAL: -> int grad W.
+    """
+    k = kernel_preset(kernel) if isinstance(kernel, int) else kernel
+    px, py, tri = _dev(px), _dev(py), _dev(tri)
+    offsets, tri_idx = _dev(offsets, torch.int64), _dev(tri_idx, torch.int32)
+    N, T, P = px.numel(), tri.shape[1], tri_idx.numel()
+    nn = 1
+    if op != OP_NORMAL:
+        fa, fb = _dev(fa), _dev(fb)
+        nn = fa.shape[0]
+        if fa.shape != (nn, T) or fb.shape != (nn, T):
+            raise SphbiError("fa, fb must both be [n_nodes, T]")
+    if op in (OP_GRAD_DIFFERENCE, OP_GRAD_SYMMETRIC):
+        qa, qb = _dev(qa), _dev(qb)
+        if qa.numel() != N or qb.numel() != N:
+            raise SphbiError("qa, qb must be [N]")
+    out_a = torch.empty(N, dtype=torch.float64, device=px.device)
+    out_b = torch.empty_like(out_a)
+    o = opts(FP64)
+    _check(lib().sphbi_operator(C.byref(k), C.byref(o), int(op), float(h), nn, N, _ptr(px), _ptr(py), _ptr(qa),
+                                _ptr(qb), T, _ptr(tri), _ptr(fa), _ptr(fb), _ptr(offsets), _ptr(tri_idx), P,
+                                _ptr(out_a), _ptr(out_b), _stream()), "sphbi_operator")
+    return out_a, out_b
+
+
+def gradient_difference(kernel, h, px, py, A_p, rho_p, tri, A, rho, offsets, tri_idx):
+    """(1/rho(x)) int rho (A - A(x)) grad W with per-node pre-weights (Sec. 2)."""
+    return operator(OP_GRAD_DIFFERENCE, kernel, h, px, py, tri, offsets, tri_idx, A, rho, A_p, rho_p)
+
+
+def gradient_symmetric(kernel, h, px, py, A_p, rho_p, tri, A, rho, offsets, tri_idx):
+    """rho(x) int rho (A/rho^2 + A(x)/rho(x)^2) grad W with per-node pre-weights (Sec. 2)."""
+    return operator(OP_GRAD_SYMMETRIC, kernel, h, px, py, tri, offsets, tri_idx, A, rho, A_p, rho_p)
+
+
+def divergence_curl(kernel, h, px, py, tri, Ax, Ay, offsets, tri_idx):
+    """(div, curl) of the boundary vector field (Ax, Ay) (Sec. 2)."""
+    return operator(OP_DIV_CURL, kernel, h, px, py, tri, offsets, tri_idx, Ax, Ay)
+
+
+def boundary_normal(kernel, h, px, py, tri, offsets, tri_idx):
+    """int grad W over the boundary, per particle (App. A)."""
+    return operator(OP_NORMAL, kernel, h, px, py, tri, offsets, tri_idx)
 
 
 # ----------------------------------------------------------------------------

@@ -572,6 +572,32 @@ int sphbi_integrate_backward(const sphbi_kernel *kernel, const sphbi_opts *opts,
                            dpy, dtri, dnodal, ws, (hipStream_t)stream);
 }
 
+int sphbi_operator(const sphbi_kernel *kernel, const sphbi_opts *opts, int32_t op, double h, int32_t n_nodes,
+                   int64_t N, const double *px, const double *py, const double *qa, const double *qb, int64_t T,
+                   const double *tri, const double *fa, const double *fb, const int64_t *offsets,
+                   const int32_t *tri_idx, int64_t n_pairs, double *out_a, double *out_b, void *stream) {
+    if (op < SPHBI_OP_GRAD_DIFFERENCE || op > SPHBI_OP_NORMAL) { set_error("unknown operator %d", op); return SPHBI_EINVAL; }
+    if (op == SPHBI_OP_NORMAL) n_nodes = 1;
+    sphbi_opts o;
+    int rc = check_common(kernel, opts, &o, h, n_nodes, N, T, n_pairs);
+    if (rc) return rc;
+    if (o.precision != SPHBI_FP64) { set_error("the operators run in FP64 only"); return SPHBI_EUNSUPPORTED; }
+    const bool grad_form = op == SPHBI_OP_GRAD_DIFFERENCE || op == SPHBI_OP_GRAD_SYMMETRIC;
+    if (N > 0 && (!px || !py || !offsets || !out_a || !out_b)) { set_error("particle arrays are NULL"); return SPHBI_EINVAL; }
+    if (N > 0 && grad_form && (!qa || !qb)) { set_error("particle values qa/qb are NULL"); return SPHBI_EINVAL; }
+    if (n_pairs > 0 && (!tri_idx || !tri)) { set_error("pair/triangle arrays are NULL"); return SPHBI_EINVAL; }
+    if (n_pairs > 0 && op != SPHBI_OP_NORMAL && (!fa || !fb)) { set_error("nodal fields fa/fb are NULL"); return SPHBI_EINVAL; }
+    const void *ptrs[] = {px, py, qa, qb, tri, fa, fb, offsets, tri_idx, out_a, out_b};
+    for (const void *p : ptrs)
+        if (!aligned8(p)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
+    if (N == 0) return SPHBI_OK;
+    int deg = 0;
+    const KArgs K = make_kargs(kernel, &deg);
+    const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
+    return launch_operator(op, order, deg, K, h, N, px, py, qa, qb, offsets, tri_idx, n_pairs, T, tri, fa, fb, out_a,
+                           out_b, (hipStream_t)stream);
+}
+
 // ----------------------------------------------------------------------------
 // learned surrogate
 // ----------------------------------------------------------------------------

@@ -265,33 +265,45 @@ __host__ __device__ inline void taylor_shift(const S *__restrict__ e, S sx, S sy
 // contraction's, and kOnLine says the edge may lie on a line through the
 // particle (p = 0), where H_0 is taken as 0 (it only ever appears times p).
 //
-// FieldSink contracts them with one field's edge-frame harmonics hv and adds
-// the value and gradient integrals (without c_d and the -1/h of the
-// gradient).
-template <typename S>
+// FieldSink contracts them with the edge-frame harmonics hv of NF fields and
+// adds each field's value and gradient integrals (without c_d and the -1/h of
+// the gradient).
+template <typename S, int NF = 1>
 struct FieldSink {
     static constexpr int kHMax = 0, kPMax = 0;
     static constexpr bool kOnLine = false;
     __host__ __device__ void radial(const KArgs &, int, S, const S *, const S *) {}
-    const Harm<S> *hv;
-    S I, X, Y;
-    Harm<S> hx, hy;
+    const Harm<S> *hv[NF];          // NF fields sharing the geometry
+    S I[NF], X[NF], Y[NF];
+    Harm<S> hx[NF], hy[NF];
     __host__ __device__ void sector(int m, double sv, double sw, const S *angc, const S *angs) {
-        Harm<S> gx, gy;
-        mul_cs(m, hv[m], gx, gy);
 #pragma unroll
-        for (int n = m & 1; n <= m; n += 2) I += sv * (hv[m].c[n] * angc[n] + hv[m].s[n] * angs[n]);
+        for (int f = 0; f < NF; ++f) {
+            Harm<S> gx, gy;
+            mul_cs(m, hv[f][m], gx, gy);
 #pragma unroll
-        for (int n = (m + 1) & 1; n <= m + 1; n += 2) {
-            X += sw * (gx.c[n] * angc[n] + gx.s[n] * angs[n]);
-            Y += sw * (gy.c[n] * angc[n] + gy.s[n] * angs[n]);
+            for (int n = m & 1; n <= m; n += 2) I[f] += sv * (hv[f][m].c[n] * angc[n] + hv[f][m].s[n] * angs[n]);
+#pragma unroll
+            for (int n = (m + 1) & 1; n <= m + 1; n += 2) {
+                X[f] += sw * (gx.c[n] * angc[n] + gx.s[n] * angs[n]);
+                Y[f] += sw * (gy.c[n] * angc[n] + gy.s[n] * angs[n]);
+            }
         }
     }
-    __host__ __device__ void begin(int m) { mul_cs(m, hv[m], hx, hy); }
-    __host__ __device__ void value(int m, int n, S vc, S vs) { I += hv[m].c[n] * vc + hv[m].s[n] * vs; }
+    __host__ __device__ void begin(int m) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) mul_cs(m, hv[f][m], hx[f], hy[f]);
+    }
+    __host__ __device__ void value(int m, int n, S vc, S vs) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) I[f] += hv[f][m].c[n] * vc + hv[f][m].s[n] * vs;
+    }
     __host__ __device__ void grad(int, int n, S wc, S ws) {
-        X += hx.c[n] * wc + hx.s[n] * ws;
-        Y += hy.c[n] * wc + hy.s[n] * ws;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            X[f] += hx[f].c[n] * wc + hx[f].s[n] * ws;
+            Y[f] += hy[f].c[n] * wc + hy[f].s[n] * ws;
+        }
     }
 };
 
@@ -796,17 +808,21 @@ __host__ __device__ inline void pair_fwd_rot(const KArgs &K, const M &math, doub
     pair_core<DEG, ORDER, S, M, EDGE_UNROLL>(K, math, tau, bx, by, area2, c, invh, oI, oX, oY);
 }
 
-// The pair for a field given as a polynomial about the particle:
-// A(x + h xi) = sum c_ij xi_x^i xi_y^j, vertices (ax, ay) in units of h
-// relative to the particle, area2 their doubled signed area (non-zero).
-// EDGE_UNROLL = 1 keeps the edge loop rolled (one edge's state live at a
-// time), 3 unrolls it.
-template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL>
-__host__ __device__ inline void pair_core(const KArgs &K, const M &math, double tau, const S *ax, const S *ay,
-                                          const S &area2, const S *c, double invh, S &oI, S &oX, S &oY) {
-    Harm<S> hg[ORDER + 1];
-    global_harmonics<ORDER, S>(c, hg);
-    S I = 0.0, GX = 0.0, GY = 0.0;
+// The pair for NF fields given as polynomials about the particle:
+// A_f(x + h xi) = sum c[10 f + k] xi^k (record order), vertices (ax, ay) in
+// units of h relative to the particle, area2 their doubled signed area
+// (non-zero).  The fields share every geometric term; only the contraction
+// with each field's harmonics is repeated.  EDGE_UNROLL = 1 keeps the edge
+// loop rolled (one edge's state live at a time), 3 unrolls it.
+template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL, int NF>
+__host__ __device__ inline void pair_core_n(const KArgs &K, const M &math, double tau, const S *ax, const S *ay,
+                                            const S &area2, const S *c, double invh, S *oI, S *oX, S *oY) {
+    Harm<S> hg[NF][ORDER + 1];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) global_harmonics<ORDER, S>(c + 10 * f, hg[f]);
+    S I[NF], GX[NF], GY[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) I[f] = GX[f] = GY[f] = 0.0;
     // the vertex registers rotate, so that the loop body is the same for every edge
     S x0 = ax[0], y0 = ay[0], x1 = ax[1], y1 = ay[1], x2 = ax[2], y2 = ay[2];
     S q0 = x0 * x0 + y0 * y0, q1 = x1 * x1 + y1 * y1, q2 = x2 * x2 + y2 * y2;   // squared radii
@@ -827,24 +843,32 @@ __host__ __device__ inline void pair_core(const KArgs &K, const M &math, double 
         // harmonics in the edge frame: theta = psi + phi, (cos phi, sin phi) = n
         S cph[4], sph[4];
         edge_phases(nx, ny, cph, sph);
-        Harm<S> hl[ORDER + 1];
+        Harm<S> hl[NF][ORDER + 1];
 #pragma unroll
-        for (int m = 0; m <= ORDER; ++m)
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
-            for (int n = 0; n < 5; ++n) {
-                if (n > 3) { hl[m].c[n] = hl[m].s[n] = 0.0; continue; }
-                const S hc = hg[m].c[n], hs = hg[m].s[n];
-                hl[m].c[n] = hc * cph[n] + hs * sph[n];
-                hl[m].s[n] = hs * cph[n] - hc * sph[n];
-            }
-        FieldSink<S> sk;
-        sk.hv = hl;
-        sk.I = sk.X = sk.Y = 0.0;
+            for (int m = 0; m <= ORDER; ++m)
+#pragma unroll
+                for (int n = 0; n < 5; ++n) {
+                    if (n > 3) { hl[f][m].c[n] = hl[f][m].s[n] = 0.0; continue; }
+                    const S hc = hg[f][m].c[n], hs = hg[f][m].s[n];
+                    hl[f][m].c[n] = hc * cph[n] + hs * sph[n];
+                    hl[f][m].s[n] = hs * cph[n] - hc * sph[n];
+                }
+        FieldSink<S, NF> sk;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            sk.hv[f] = hl[f];
+            sk.I[f] = sk.X[f] = sk.Y[f] = 0.0;
+        }
         const auto em = math.for_edge(p, tau);
         for (int pc = 0; pc < K.npieces; ++pc) edge_piece<DEG, ORDER, S>(K, em, pc, p, ya, yb, ra2, rb2, sk);
-        I += sk.I;
-        GX += sk.X * nx - sk.Y * ny;
-        GY += sk.X * ny + sk.Y * nx;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            I[f] += sk.I[f];
+            GX[f] += sk.X[f] * nx - sk.Y[f] * ny;
+            GY[f] += sk.X[f] * ny + sk.Y[f] * nx;
+        }
     }
     // an edge skipped (particle on its line, or zero length) leaves the ray
     // terms of its neighbours at its two vertices without partners
@@ -853,13 +877,26 @@ __host__ __device__ inline void pair_core(const KArgs &K, const M &math, double 
         for (int v = 0; v < 3; ++v) {
             // vertex v starts edge v and ends edge v-1
             const bool out = skipped & (1 << v), in = skipped & (1 << (v == 0 ? 2 : v - 1));
-            if (out != in) vertex_ray_terms<ORDER, S>(K, math, hg, ax[v], ay[v], out ? 1.0 : -1.0, I, GX, GY);
+            if (out != in)
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+                    vertex_ray_terms<ORDER, S>(K, math, hg[f], ax[v], ay[v], out ? 1.0 : -1.0, I[f], GX[f], GY[f]);
         }
     }
     const double sg = area2 > 0.0 ? K.cd : -K.cd;
-    oI = sg * I;
-    oX = -sg * invh * GX;
-    oY = -sg * invh * GY;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        oI[f] = sg * I[f];
+        oX[f] = -sg * invh * GX[f];
+        oY[f] = -sg * invh * GY[f];
+    }
+}
+
+// The pair for one field.
+template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL>
+__host__ __device__ inline void pair_core(const KArgs &K, const M &math, double tau, const S *ax, const S *ay,
+                                          const S &area2, const S *c, double invh, S &oI, S &oX, S &oY) {
+    pair_core_n<DEG, ORDER, S, M, EDGE_UNROLL, 1>(K, math, tau, ax, ay, area2, c, invh, &oI, &oX, &oY);
 }
 
 // ----------------------------------------------------------------------------

@@ -1,0 +1,148 @@
+"""Pins of the oracle's SPH operators (Sec. 2 and App. A) against what the
+mathematics fixes, independently of the closed forms:
+
+* consistency of the continuous operators with full kernel support (a particle
+  whose support disc lies inside the meshed region): for a normalised kernel
+  int grad W = 0 and int (x' - x)_j d_i W(x - x') dx' = delta_ij, so the
+  difference and symmetric gradients of a linear field with constant density
+  are its gradient, and the divergence and curl of a linear vector field are
+  the trace and the antisymmetric part of its matrix;
+* pre-weights that vanish: the difference gradient of a constant field is 0
+  for any density, also at a wall;
+* a straight wall (half-plane boundary) at distance d: by the divergence
+  theorem int_{y'<0} grad_x W(x - x') dx' = (0, -int_line W ds), a 1D integral
+  taken here by adaptive quadrature of the kernel polynomial; the symmetric
+  gradient of a constant c with constant density is 2 c times that normal,
+  which also fixes the sign of the symmetric pre-weights (a minus would give
+  0);
+* pairs with an out-of-range triangle index contribute nothing.
+"""
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+import oracle
+from oracle import operators as O
+from paper_2507_21686_amd import workloads as W
+
+H = 0.5
+
+
+def full_support_case(seed=0, n=16):
+    tri = W.box_mesh_random(6, 8, seed=seed)           # covers [-1, 1]^2
+    rng = np.random.default_rng(seed + 1)
+    px = rng.uniform(-0.45, 0.45, n)                    # support disc of radius 0.5 inside
+    py = rng.uniform(-0.45, 0.45, n)
+    off, idx = oracle.pairlist(px, py, tri, H)
+    return tri, px, py, off, idx
+
+
+def nodes(tri, order):
+    return W.vertex_positions(tri) if order == 1 else W.cubic_node_positions(tri)
+
+
+def line_integral_of_W(kid, h, d):
+    """int over the line y' = 0 of W(|x - x'|) for a particle at distance d."""
+    n_pieces, R, deg, b, cd = oracle.kernel_monomials(kid)
+    dd = d / h
+    total = 0.0
+    for p in range(n_pieces):
+        if dd >= R[p]:
+            continue
+        half = np.sqrt(R[p] ** 2 - dd ** 2)
+        coeff = b[p][: deg[p] + 1]
+        f = lambda s: sum(c * np.sqrt(s * s + dd * dd) ** k for k, c in enumerate(coeff))
+        total += 2.0 * quad(f, 0.0, half, epsabs=0.0, epsrel=1e-12, limit=200)[0]     # even in s
+    return cd / h * total
+
+
+def wall_case(d_list):
+    L = 4.0 * H
+    tri = np.array([[-L, -L, L, -L, L, 0.0], [-L, -L, L, 0.0, -L, 0.0]]).T.copy()   # y' in [-L, 0]
+    px = np.linspace(-0.3, 0.3, len(d_list))
+    py = np.asarray(d_list, dtype=float)
+    off, idx = oracle.pairlist(px, py, tri, H)
+    return tri, px, py, off, idx
+
+
+@pytest.mark.parametrize("kid", [0, 1, 2, 3])
+@pytest.mark.parametrize("order", [1, 3])
+def test_linear_field_gradients_full_support(kid, order):
+    tri, px, py, off, idx = full_support_case(seed=kid)
+    X = nodes(tri, order)
+    a = np.array([0.7, -1.3])
+    A = 5.0 + a[0] * X[:, 0] + a[1] * X[:, 1]
+    rho = np.full_like(A, 1000.0)
+    Ap = 5.0 + a[0] * px + a[1] * py
+    rp = np.full_like(px, 1000.0)
+    for fn in (O.gradient_difference, O.gradient_symmetric):
+        gx, gy = fn(kid, H, px, py, Ap, rp, tri, A, rho, off, idx)
+        assert np.abs(gx - a[0]).max() < 1e-12
+        assert np.abs(gy - a[1]).max() < 1e-12
+
+
+@pytest.mark.parametrize("kid", [0, 1, 2, 3])
+@pytest.mark.parametrize("order", [1, 3])
+def test_linear_vector_field_div_curl_full_support(kid, order):
+    tri, px, py, off, idx = full_support_case(seed=10 + kid)
+    X = nodes(tri, order)
+    M = np.array([[0.4, -2.1], [1.7, 0.9]])
+    Ax = 0.3 + M[0, 0] * X[:, 0] + M[0, 1] * X[:, 1]
+    Ay = -1.1 + M[1, 0] * X[:, 0] + M[1, 1] * X[:, 1]
+    div, curl = O.divergence_curl(kid, H, px, py, tri, Ax, Ay, off, idx)
+    assert np.abs(div - (M[0, 0] + M[1, 1])).max() < 1e-12
+    assert np.abs(curl - (M[1, 0] - M[0, 1])).max() < 1e-12
+
+
+@pytest.mark.parametrize("kid", [0, 1, 2, 3])
+def test_normal_full_support_vanishes(kid):
+    tri, px, py, off, idx = full_support_case(seed=20 + kid)
+    nx, ny = O.boundary_normal(kid, H, px, py, tri, off, idx)
+    assert np.abs(nx).max() < 1e-13 / H and np.abs(ny).max() < 1e-13 / H
+
+
+@pytest.mark.parametrize("kid", [0, 1, 2, 3])
+def test_wall_normal_and_symmetric_constant(kid):
+    d = [0.05 * H, 0.3 * H, 0.55 * H, 0.9 * H, 0.999 * H]
+    tri, px, py, off, idx = wall_case(d)
+    nx, ny = O.boundary_normal(kid, H, px, py, tri, off, idx)
+    ref = np.array([line_integral_of_W(kid, H, di) for di in d])
+    assert np.abs(nx).max() < 1e-12 * np.abs(ref).max()
+    assert np.abs(ny + ref).max() < 1e-11 * np.abs(ref).max()
+    # symmetric gradient of a constant c with constant density: 2 c n
+    c, rho0 = 3.25, 997.0
+    A = np.full((3, tri.shape[1]), c)
+    rho = np.full_like(A, rho0)
+    gx, gy = O.gradient_symmetric(kid, H, px, py, np.full(len(d), c), np.full(len(d), rho0), tri, A, rho, off, idx)
+    assert np.abs(gx - 2 * c * nx).max() < 1e-12 * np.abs(ref).max() * c
+    assert np.abs(gy - 2 * c * ny).max() < 1e-12 * np.abs(ref).max() * c
+    # difference gradient of a constant: the pre-weights vanish
+    gx, gy = O.gradient_difference(kid, H, px, py, np.full(len(d), c), np.full(len(d), rho0), tri, A, rho, off, idx)
+    assert np.all(gx == 0.0) and np.all(gy == 0.0)
+
+
+def test_difference_constant_field_any_density():
+    tri, px, py, off, idx = full_support_case(seed=3)
+    rng = np.random.default_rng(5)
+    rho = rng.uniform(500.0, 1500.0, (10, tri.shape[1]))
+    A = np.full_like(rho, -7.5)
+    gx, gy = O.gradient_difference(1, H, px, py, np.full(px.shape, -7.5), rng.uniform(900, 1100, px.shape), tri, A,
+                                   rho, off, idx)
+    assert np.all(gx == 0.0) and np.all(gy == 0.0)
+
+
+def test_out_of_range_pairs_contribute_nothing():
+    tri, px, py, off, idx = full_support_case(seed=4, n=6)
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((3, tri.shape[1]))
+    rho = rng.uniform(0.5, 1.5, A.shape)
+    Ap, rp = rng.standard_normal(px.shape), rng.uniform(0.5, 1.5, px.shape)
+    ref = O.gradient_difference(0, H, px, py, Ap, rp, tri, A, rho, off, idx)
+    # append an invalid pair to every particle
+    off2 = off + np.arange(len(off))
+    idx2 = np.empty(len(idx) + len(px), np.int32)
+    for i in range(len(px)):
+        idx2[off2[i]:off2[i + 1] - 1] = idx[off[i]:off[i + 1]]
+        idx2[off2[i + 1] - 1] = tri.shape[1] + 5 if i % 2 else -1
+    got = O.gradient_difference(0, H, px, py, Ap, rp, tri, A, rho, off2, idx2)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
