@@ -212,19 +212,23 @@ int sphbi_integrate_backward(const sphbi_kernel *kernel /* host */, const sphbi_
  *
  * "grad" is with respect to the particle position (as G of
  * sphbi_integrate, 1/h included).  Densities must be non-zero.  Pair list,
- * kernel and h as in sphbi_integrate.  FP64 only (opts may be NULL; MIXED
- * is rejected with SPHBI_EUNSUPPORTED).  No workspace.  Asynchronous.
+ * kernel and h as in sphbi_integrate.  ws: device workspace of
+ * sphbi_operator_workspace(N, T) bytes (two per-triangle records and two
+ * per-particle arrays); the call overwrites it.  FP64 only (opts may be
+ * NULL; MIXED is rejected with SPHBI_EUNSUPPORTED).  Asynchronous.
  * ------------------------------------------------------------------- */
 #define SPHBI_OP_GRAD_DIFFERENCE 0
 #define SPHBI_OP_GRAD_SYMMETRIC 1
 #define SPHBI_OP_DIV_CURL 2
 #define SPHBI_OP_NORMAL 3
 
+size_t sphbi_operator_workspace(int64_t N, int64_t T);
+
 int sphbi_operator(const sphbi_kernel *kernel /* host */, const sphbi_opts *opts /* host, NULL = default */,
                    int32_t op, double h, int32_t n_nodes, int64_t N, const double *px, const double *py,
                    const double *qa, const double *qb, int64_t T, const double *tri, const double *fa,
                    const double *fb, const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, double *out_a,
-                   double *out_b, void *stream);
+                   double *out_b, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------
  * Learned surrogate of the per-pair result (an extension; the paper has no

@@ -80,8 +80,10 @@ def lib():
         L.sphbi_integrate_backward.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, i32, i64, vp, vp,
                                                i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp,
                                                C.c_size_t, vp]
+        L.sphbi_operator_workspace.argtypes = [i64, i64]
+        L.sphbi_operator_workspace.restype = C.c_size_t
         L.sphbi_operator.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), i32, d, i32, i64, vp, vp, vp,
-                                     vp, i64, vp, vp, vp, vp, vp, i64, vp, vp, vp]
+                                     vp, i64, vp, vp, vp, vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
         f = C.c_float
         L.sphbi_surrogate_features.argtypes = [d, i64, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
         L.sphbi_surrogate_targets.argtypes = [i64, d, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
@@ -279,12 +281,13 @@ def integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx, per_pair=False, p
 OP_GRAD_DIFFERENCE, OP_GRAD_SYMMETRIC, OP_DIV_CURL, OP_NORMAL = 0, 1, 2, 3
 
 
-def operator(op, kernel, h, px, py, tri, offsets, tri_idx, fa=None, fb=None, qa=None, qb=None):
+def operator(op, kernel, h, px, py, tri, offsets, tri_idx, fa=None, fb=None, qa=None, qb=None, ws=None):
     """``sphbi_operator``: two per-particle outputs [N] of operator ``op``.
 
     OP_GRAD_DIFFERENCE / OP_GRAD_SYMMETRIC: fa = A, fb = rho nodal [n_nodes, T],
     qa = A(x), qb = rho(x) [N] -> (d/dx, d/dy); OP_DIV_CURL: fa = A_x, fb = A_y
-    -> (div, curl); OP_NORMAL: -> int grad W.
+    -> (div, curl); OP_NORMAL: -> int grad W.  ``ws``: optional uint8 device
+    workspace of at least ``sphbi_operator_workspace(N, T)`` bytes.
     """
     k = kernel_preset(kernel) if isinstance(kernel, int) else kernel
     px, py, tri = _dev(px), _dev(py), _dev(tri)
@@ -302,10 +305,12 @@ def operator(op, kernel, h, px, py, tri, offsets, tri_idx, fa=None, fb=None, qa=
             raise SphbiError("qa, qb must be [N]")
     out_a = torch.empty(N, dtype=torch.float64, device=px.device)
     out_b = torch.empty_like(out_a)
+    if ws is None or ws.numel() < int(lib().sphbi_operator_workspace(N, T)):
+        ws = torch.empty(int(lib().sphbi_operator_workspace(N, T)), dtype=torch.uint8, device=px.device)
     o = opts(FP64)
     _check(lib().sphbi_operator(C.byref(k), C.byref(o), int(op), float(h), nn, N, _ptr(px), _ptr(py), _ptr(qa),
                                 _ptr(qb), T, _ptr(tri), _ptr(fa), _ptr(fb), _ptr(offsets), _ptr(tri_idx), P,
-                                _ptr(out_a), _ptr(out_b), _stream()), "sphbi_operator")
+                                _ptr(out_a), _ptr(out_b), _ptr(ws), ws.numel(), _stream()), "sphbi_operator")
     return out_a, out_b
 
 

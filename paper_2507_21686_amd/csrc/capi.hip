@@ -572,10 +572,13 @@ int sphbi_integrate_backward(const sphbi_kernel *kernel, const sphbi_opts *opts,
                            dpy, dtri, dnodal, ws, (hipStream_t)stream);
 }
 
+size_t sphbi_operator_workspace(int64_t N, int64_t T) { return operator_workspace(N, T); }
+
 int sphbi_operator(const sphbi_kernel *kernel, const sphbi_opts *opts, int32_t op, double h, int32_t n_nodes,
                    int64_t N, const double *px, const double *py, const double *qa, const double *qb, int64_t T,
                    const double *tri, const double *fa, const double *fb, const int64_t *offsets,
-                   const int32_t *tri_idx, int64_t n_pairs, double *out_a, double *out_b, void *stream) {
+                   const int32_t *tri_idx, int64_t n_pairs, double *out_a, double *out_b, void *ws, size_t ws_bytes,
+                   void *stream) {
     if (op < SPHBI_OP_GRAD_DIFFERENCE || op > SPHBI_OP_NORMAL) { set_error("unknown operator %d", op); return SPHBI_EINVAL; }
     if (op == SPHBI_OP_NORMAL) n_nodes = 1;
     sphbi_opts o;
@@ -586,16 +589,19 @@ int sphbi_operator(const sphbi_kernel *kernel, const sphbi_opts *opts, int32_t o
     if (N > 0 && (!px || !py || !offsets || !out_a || !out_b)) { set_error("particle arrays are NULL"); return SPHBI_EINVAL; }
     if (N > 0 && grad_form && (!qa || !qb)) { set_error("particle values qa/qb are NULL"); return SPHBI_EINVAL; }
     if (n_pairs > 0 && (!tri_idx || !tri)) { set_error("pair/triangle arrays are NULL"); return SPHBI_EINVAL; }
-    if (n_pairs > 0 && op != SPHBI_OP_NORMAL && (!fa || !fb)) { set_error("nodal fields fa/fb are NULL"); return SPHBI_EINVAL; }
-    const void *ptrs[] = {px, py, qa, qb, tri, fa, fb, offsets, tri_idx, out_a, out_b};
+    if (T > 0 && !tri) { set_error("triangle array is NULL"); return SPHBI_EINVAL; }
+    if (T > 0 && op != SPHBI_OP_NORMAL && (!fa || !fb)) { set_error("nodal fields fa/fb are NULL"); return SPHBI_EINVAL; }
+    const void *ptrs[] = {px, py, qa, qb, tri, fa, fb, offsets, tri_idx, out_a, out_b, ws};
     for (const void *p : ptrs)
         if (!aligned8(p)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
     if (N == 0) return SPHBI_OK;
+    const size_t need = operator_workspace(N, T);
+    if (!ws || ws_bytes < need) { set_error("workspace too small (%zu < %zu)", ws_bytes, need); return SPHBI_ENOWORKSPACE; }
     int deg = 0;
     const KArgs K = make_kargs(kernel, &deg);
     const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
     return launch_operator(op, order, deg, K, h, N, px, py, qa, qb, offsets, tri_idx, n_pairs, T, tri, fa, fb, out_a,
-                           out_b, (hipStream_t)stream);
+                           out_b, ws, (hipStream_t)stream);
 }
 
 // ----------------------------------------------------------------------------

@@ -52,11 +52,13 @@ int launch_backward(int order, int deg, const KArgs &K, double h, int64_t N, con
                     const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,
                     const double *nodal, const double *gI, const double *gX, const double *gY, double *dpx,
                     double *dpy, double *dtri, double *dnodal, void *ws, hipStream_t s);
-// SPH operators on the boundary (op: SPHBI_OP_*), outputs [N] each
+// SPH operators on the boundary (op: SPHBI_OP_*), outputs [N] each; ws of
+// operator_workspace(N, T) bytes
+size_t operator_workspace(int64_t N, int64_t T);
 int launch_operator(int op, int order, int deg, const KArgs &K, double h, int64_t N, const double *px,
                     const double *py, const double *qa, const double *qb, const int64_t *off, const int32_t *tri_idx,
                     int64_t P, int64_t T, const double *tri, const double *fa, const double *fb, double *out_a,
-                    double *out_b, hipStream_t s);
+                    double *out_b, void *ws, hipStream_t s);
 // the adjoint pair kernel for linear fields (its own translation unit)
 void launch_adjoint_linear(int deg, const KArgs &K, double invh, int64_t N, const double *px, const double *py,
                            const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,

@@ -234,12 +234,15 @@ def test_operator_edge_cases():
     toff, tidx = dev(off, torch.int64), dev(idx, torch.int32)
     out = torch.empty(wl.n_particles, dtype=torch.float64, device=DEV)
     P = int(idx.shape[0])
-    args = lambda op, oo, fa: (C.byref(k), C.byref(oo), op, wl.h, 3, wl.n_particles, sb._ptr(tpx), sb._ptr(tpy),
-                               sb._ptr(dev(Ap)), sb._ptr(dev(rp)), wl.n_triangles, sb._ptr(ttri), fa,
-                               sb._ptr(dev(rho)), sb._ptr(toff), sb._ptr(tidx), P, sb._ptr(out), sb._ptr(out),
-                               sb._stream())
+    need = int(L.sphbi_operator_workspace(wl.n_particles, wl.n_triangles))
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    args = lambda op, oo, fa, nbytes=need: (C.byref(k), C.byref(oo), op, wl.h, 3, wl.n_particles, sb._ptr(tpx),
+                                            sb._ptr(tpy), sb._ptr(dev(Ap)), sb._ptr(dev(rp)), wl.n_triangles,
+                                            sb._ptr(ttri), fa, sb._ptr(dev(rho)), sb._ptr(toff), sb._ptr(tidx), P,
+                                            sb._ptr(out), sb._ptr(out), sb._ptr(ws), nbytes, sb._stream())
     assert L.sphbi_operator(*args(7, o, sb._ptr(dev(A)))) == -1
     assert L.sphbi_operator(*args(0, o, C.c_void_p(None))) == -1
     om = sb.opts(sb.MIXED)
     assert L.sphbi_operator(*args(0, om, sb._ptr(dev(A)))) == -2
+    assert L.sphbi_operator(*args(0, o, sb._ptr(dev(A)), need - 1)) == -4
     torch.cuda.synchronize()
