@@ -42,14 +42,18 @@
 // the logarithm of the radial term, the radial recurrences, the kernel
 // contraction and the per-particle sums in FP64.
 //
-// COMB (combined fields, used by the SPH operators): the field of a pair is
-// the record's field plus (beta_T - gam[particle]) times a second field of
-// the same triangle (rec2: its ten coefficients, then beta_T), formed in the
-// pair's registers before the evaluation.
+// Field modes (FM), for the SPH operators:
+//   kFieldPlain   the record's field: (I, Gx, Gy);
+//   kFieldComb    the record's field plus (beta_T - gam[particle]) times a
+//                 second field of the same triangle (rec2: its ten
+//                 coefficients, then beta_T), formed in the pair's registers
+//                 before the evaluation: (I, Gx, Gy) of the combination;
+//   kFieldDivCurl the record's field as A_x and rec2's as A_y, both through
+//                 one closed-form pass: (0, div, curl).
 //
 // This header is included by forward.hip (plain fields) and operators.hip
-// (combined fields); the anonymous namespace keeps each unit's instantiations
-// its own.
+// (the other modes); the anonymous namespace keeps each unit's
+// instantiations its own.
 
 #pragma once
 
@@ -60,6 +64,8 @@
 
 namespace sphbi {
 namespace {
+
+constexpr int kFieldPlain = 0, kFieldComb = 1, kFieldDivCurl = 2;
 
 // The pair's record with the combined field: coefficients e + s e2,
 // s = rec2[10] - g.
@@ -87,7 +93,43 @@ __host__ __device__ constexpr int fwd_waves(int deg, int order, bool) {
 }
 __host__ __device__ constexpr int fwd_edge_unroll(int deg, int order) { return order >= 2 && deg > 8 ? 1 : 3; }
 
-template <int DEG, int ORDER, bool MIXED, bool COMB>
+// Divergence and curl of one pair, the vertices taken from rot on (see
+// pair_fwd_rot): A_x from the record r, A_y from the coefficients r2, both
+// through one closed-form pass (pair_core_n).  Compiled for two waves per
+// SIMD with the cubic edge loop rolled: for cubic fields the two fields'
+// harmonics then spill about 120 B per lane, and that still runs a quarter
+// faster than one wave without spills (0.77 vs 1.04 ms on the covering mesh).
+__host__ __device__ constexpr int dc_waves(int) { return 2; }
+template <int DEG, int ORDER>
+__device__ inline void pair_div_curl_rot(const KArgs &K, double x, double y, double invh, const double *__restrict__ r,
+                                         const double *__restrict__ r2, int rot, double &div, double &curl) {
+    div = curl = 0.0;
+    double ax[3], ay[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        ax[i] = (r[2 * i] - x) * invh;
+        ay[i] = (r[2 * i + 1] - y) * invh;
+    }
+    const double area2 = (ax[1] - ax[0]) * (ay[2] - ay[0]) - (ax[2] - ax[0]) * (ay[1] - ay[0]);
+    if (area2 == 0.0) return;
+    double c[20];
+    taylor_shift<ORDER, double>(r + 6, ax[0], ay[0], c);
+    taylor_shift<ORDER, double>(r2, ax[0], ay[0], c + 10);
+    double bx[3], by[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int j1 = i == 2 ? 0 : i + 1, j2 = i == 0 ? 2 : i - 1;
+        bx[i] = rot == 0 ? ax[i] : (rot == 1 ? ax[j1] : ax[j2]);
+        by[i] = rot == 0 ? ay[i] : (rot == 1 ? ay[j1] : ay[j2]);
+    }
+    double oI[2], oX[2], oY[2];
+    pair_core_n<DEG, ORDER, double, ExactMath, ORDER >= 2 ? 1 : 3, 2>(K, ExactMath(), 0.0, bx, by, area2, c, invh, oI,
+                                                                      oX, oY);
+    div = oX[0] + oY[1];
+    curl = oX[1] - oY[0];
+}
+
+template <int DEG, int ORDER, bool MIXED, int FM>
 __global__ __launch_bounds__(256, fwd_waves(DEG, ORDER, MIXED)) void forward_kernel(const KArgs K, double tau, double invh, int64_t N,
                                                       const double *__restrict__ px,
                                                       const double *__restrict__ py,
@@ -127,8 +169,8 @@ __global__ __launch_bounds__(256, fwd_waves(DEG, ORDER, MIXED)) void forward_ker
             if (t >= 0 && t < T) {   // out-of-range triangle indices contribute nothing
                 const double *r = rec + (int64_t)t * kRecDoubles;
                 constexpr int EU = fwd_edge_unroll(DEG, ORDER);
-                [[maybe_unused]] double rc[COMB ? kRecDoubles : 1];
-                if constexpr (COMB) {
+                [[maybe_unused]] double rc[FM == kFieldComb ? kRecDoubles : 1];
+                if constexpr (FM == kFieldComb) {
                     combine_record<ORDER>(r, rec2 + (int64_t)t * kRecDoubles, gam[ip], rc);
                     r = rc;
                 }
@@ -183,8 +225,8 @@ __global__ __launch_bounds__(256, fwd_waves(DEG, ORDER, MIXED)) void forward_ker
 // the same edge slots in every lane.  Results go to LDS by pair and every
 // particle sums its own pairs in pair order, so the result does not depend on
 // the sort and stays deterministic.
-template <int DEG, int ORDER, bool MIXED, int SW, bool COMB>
-__global__ __launch_bounds__(256, fwd_waves(DEG, ORDER, MIXED)) void forward_sorted_kernel(
+template <int DEG, int ORDER, bool MIXED, int SW, int FM>
+__global__ __launch_bounds__(256, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_waves(DEG, ORDER, MIXED)) void forward_sorted_kernel(
     const KArgs K, double tau, double invh, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
     const int64_t *__restrict__ off, const int32_t *__restrict__ tri_idx, const double *__restrict__ rec,
     double *__restrict__ I, double *__restrict__ Gx, double *__restrict__ Gy, double *__restrict__ per_pair, int64_t P,
@@ -284,16 +326,22 @@ __global__ __launch_bounds__(256, fwd_waves(DEG, ORDER, MIXED)) void forward_sor
                 const int32_t t = tri_idx[q];
                 if (t >= 0 && t < T) {
                     const double *r = rec + (int64_t)t * kRecDoubles;
-                    [[maybe_unused]] double rc[COMB ? kRecDoubles : 1];
-                    if constexpr (COMB) {
-                        combine_record<ORDER>(r, rec2 + (int64_t)t * kRecDoubles, gam[ip], rc);
-                        r = rc;
+                    if constexpr (FM == kFieldDivCurl) {
+                        pair_div_curl_rot<DEG, ORDER>(K, px[ip], py[ip], invh, r, rec2 + (int64_t)t * kRecDoubles,
+                                                      key & 3, vX, vY);
+                    } else {
+                        [[maybe_unused]] double rc[FM == kFieldComb ? kRecDoubles : 1];
+                        if constexpr (FM == kFieldComb) {
+                            combine_record<ORDER>(r, rec2 + (int64_t)t * kRecDoubles, gam[ip], rc);
+                            r = rc;
+                        }
+                        if (MIXED)
+                            pair_fwd_rot<DEG, ORDER, double, MixedMath, EU>(K, MixedMath{false, ORDER >= 2}, tau,
+                                                                            px[ip], py[ip], invh, r, key & 3, vI, vX,
+                                                                            vY);
+                        else pair_fwd_rot<DEG, ORDER, double, ExactMath, EU>(K, ExactMath(), 0.0, px[ip], py[ip], invh,
+                                                                             r, key & 3, vI, vX, vY);
                     }
-                    if (MIXED)
-                        pair_fwd_rot<DEG, ORDER, double, MixedMath, EU>(K, MixedMath{false, ORDER >= 2}, tau, px[ip],
-                                                                        py[ip], invh, r, key & 3, vI, vX, vY);
-                    else pair_fwd_rot<DEG, ORDER, double, ExactMath, EU>(K, ExactMath(), 0.0, px[ip], py[ip], invh, r,
-                                                                         key & 3, vI, vX, vY);
                 }
                 if (per_pair) {
                     per_pair[q] = vI;
@@ -345,27 +393,27 @@ struct FwdArgs {
     const double *rec2, *gam;      // combined fields only
 };
 
-template <int DEG, int ORDER, bool MIXED, bool COMB>
+template <int DEG, int ORDER, bool MIXED, int FM>
 void launch_fwd_t(const KArgs &K, const FwdArgs &a, hipStream_t s) {
     const int64_t waves = (a.N + 63) / 64;
     const int64_t blocks = (waves + 3) / 4;
     constexpr int SW = ORDER >= 2 ? 512 : 256;     // LDS: 56 or 28 KB per block
-    if (fwd_sorted(DEG, ORDER))
-        hipLaunchKernelGGL((forward_sorted_kernel<DEG, ORDER, MIXED, SW, COMB>), dim3((unsigned)blocks), dim3(256), 0,
+    if constexpr (fwd_sorted(DEG, ORDER) || FM == kFieldDivCurl)
+        hipLaunchKernelGGL((forward_sorted_kernel<DEG, ORDER, MIXED, SW, FM>), dim3((unsigned)blocks), dim3(256), 0,
                            s, K, a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair,
                            a.P, a.T, a.rec2, a.gam);
     else
-        hipLaunchKernelGGL((forward_kernel<DEG, ORDER, MIXED, COMB>), dim3((unsigned)blocks), dim3(256), 0, s, K,
+        hipLaunchKernelGGL((forward_kernel<DEG, ORDER, MIXED, FM>), dim3((unsigned)blocks), dim3(256), 0, s, K,
                            a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair, a.P,
                            a.T, a.rec2, a.gam);
 }
 
-template <int ORDER, bool MIXED, bool COMB = false>
+template <int ORDER, bool MIXED, int FM = kFieldPlain>
 void launch_fwd_deg(int deg, const KArgs &K, const FwdArgs &a, hipStream_t s) {
-    if (deg <= 3) launch_fwd_t<3, ORDER, MIXED, COMB>(K, a, s);
-    else if (deg <= 5) launch_fwd_t<5, ORDER, MIXED, COMB>(K, a, s);
-    else if (deg <= 8) launch_fwd_t<8, ORDER, MIXED, COMB>(K, a, s);
-    else launch_fwd_t<11, ORDER, MIXED, COMB>(K, a, s);
+    if (deg <= 3) launch_fwd_t<3, ORDER, MIXED, FM>(K, a, s);
+    else if (deg <= 5) launch_fwd_t<5, ORDER, MIXED, FM>(K, a, s);
+    else if (deg <= 8) launch_fwd_t<8, ORDER, MIXED, FM>(K, a, s);
+    else launch_fwd_t<11, ORDER, MIXED, FM>(K, a, s);
 }
 
 }  // namespace
