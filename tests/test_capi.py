@@ -83,3 +83,32 @@ def test_bad_arguments_rejected_without_device():
 def test_workspace_size():
     assert sb.lib().sphbi_integrate_workspace(1000) == 1000 * 16 * 8
     assert sb.lib().sphbi_integrate_workspace(0) >= 8
+
+
+def test_operator_arguments_rejected_without_device():
+    """sphbi_operator validates before any launch: unknown operator, mixed
+    precision, missing particle values or fields, and a short workspace."""
+    import numpy as np
+    L = sb.lib()
+    k = sb.kernel_preset(0)
+    o = sb.opts()
+    z = C.c_void_p(None)
+    N, T = 4, 2
+    host = np.zeros(64, dtype=np.float64)            # stand-in pointers: never dereferenced on these paths
+    p = C.c_void_p(host.ctypes.data)
+    need = int(L.sphbi_operator_workspace(N, T))
+    assert need >= 2 * T * 128 + 2 * N * 8
+
+    def call(op, opts, qa=p, fa=p, ws_bytes=need):
+        return L.sphbi_operator(C.byref(k), C.byref(opts), op, 1.0, 3, N, p, p, qa, p, T, p, fa, p, p, p, 8, p, p,
+                                p, ws_bytes, z)
+
+    assert call(7, o) == -1 and b"unknown operator" in L.sphbi_last_error()
+    om = sb.opts(sb.MIXED)
+    assert call(sb.OP_GRAD_DIFFERENCE, om) == -2
+    assert call(sb.OP_GRAD_DIFFERENCE, o, qa=z) == -1
+    assert call(sb.OP_DIV_CURL, o, fa=z) == -1
+    assert call(sb.OP_GRAD_SYMMETRIC, o, ws_bytes=need - 8) == -4
+    # N = 0 is a no-op
+    assert L.sphbi_operator(C.byref(k), C.byref(o), 0, 1.0, 3, 0, z, z, z, z, 0, z, z, z, z, z, 0, z, z, z, 0,
+                            z) == 0
