@@ -396,7 +396,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": measured_traffic() if args.n_side == 1024 else None,
-                     "kernel": "forward_sorted_kernel<5,3,false,512,false>", "kernel_ms": kern_avg, "flop_per_pair": flops / P,
+                     "kernel": "forward_sorted_kernel<5,3,false,512,0>", "kernel_ms": kern_avg, "flop_per_pair": flops / P,
                      "alg_bytes_per_launch": alg_bytes},
         "pairlist_ms": {"first": pairlist_ms, "warm": pairlist_ms_warm},
         "modes": {
