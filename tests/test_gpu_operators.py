@@ -246,3 +246,15 @@ def test_operator_edge_cases():
     assert L.sphbi_operator(*args(0, om, sb._ptr(dev(A)))) == -2
     assert L.sphbi_operator(*args(0, o, sb._ptr(dev(A)), need - 1)) == -4
     torch.cuda.synchronize()
+
+
+def test_operator_deterministic():
+    """Per-particle sums in pair order: reruns are bitwise identical."""
+    wl = W.covering_workload(n_side=96, nx=12, ny=24, seed=13, kernel=sb.WENDLAND_C4, field_order=3)
+    say(f"operator determinism {wl.name}")
+    off, idx = oracle.pairlist(wl.px, wl.py, wl.tri, wl.h, nthreads=NTH)
+    A, rho, Ay, Ap, rp = fields(wl, 14)
+    for op in OPS:
+        a = gpu_op(op, wl, off, idx, A, rho, Ay, Ap, rp)
+        b = gpu_op(op, wl, off, idx, A, rho, Ay, Ap, rp)
+        assert all(np.array_equal(x, y) for x, y in zip(a, b)), OPS[op]
