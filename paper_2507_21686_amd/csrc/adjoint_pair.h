@@ -45,7 +45,7 @@ namespace sphbi {
 namespace {
 
 template <int DEG, int ORDER>
-__global__ __launch_bounds__(256) void adjoint_kernel(const KArgs K, double invh, int64_t N,
+__global__ __launch_bounds__(64) void adjoint_kernel(const KArgs K, double invh, int64_t N,
                                                       const double *__restrict__ px, const double *__restrict__ py,
                                                       const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ tri_idx, int64_t P, int64_t T,
@@ -194,9 +194,9 @@ void launch_adj_deg(int deg, const KArgs &K, double invh, int64_t N, const doubl
                     const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,
                     const double *nodal, const double *gI, const double *gX, const double *gY, double *dpx,
                     double *dpy, double *pair_grad, hipStream_t s) {
-    const unsigned blocks = (unsigned)(((N + 63) / 64 + 3) / 4);
+    const unsigned blocks = (unsigned)((N + 63) / 64);
 #define SPHBI_ADJ(DG)                                                                                            \
-    hipLaunchKernelGGL((adjoint_kernel<DG, ORDER>), dim3(blocks), dim3(256), 0, s, K, invh, N, px, py, off,    \
+    hipLaunchKernelGGL((adjoint_kernel<DG, ORDER>), dim3(blocks), dim3(64), 0, s, K, invh, N, px, py, off,    \
                        tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy, pair_grad)
     if (deg <= 3) SPHBI_ADJ(3);
     else if (deg <= 5) SPHBI_ADJ(5);
