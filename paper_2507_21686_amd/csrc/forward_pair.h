@@ -84,12 +84,12 @@ __device__ inline void combine_record(const double *__restrict__ r, const double
 // budget is 512 / waves).  A single wavefront issues an FP64 operation only
 // every 5-7 cycles even with independent work (measured on gfx950), so more
 // resident waves raise the issue rate as long as the register cut costs
-// little spilling.  The table is the fastest of 1-4 waves per instantiation
-// on the covering workload (cubic fields 2, linear 3, constant 4 but 3 for the
-// degree-11 kernel); the cubic-field degree-11 variant keeps its edge loop
-// rolled to fit two waves.
+// little spilling.  The table is the fastest of 1-5 waves per instantiation
+// on the covering workload (cubic fields 2, linear 3 but 4 for the degree-3
+// kernel, constant 4 but 3 for the degree-11 kernel); the cubic-field
+// degree-11 variant keeps its edge loop rolled to fit two waves.
 __host__ __device__ constexpr int fwd_waves(int deg, int order, bool) {
-    return order >= 2 ? 2 : order == 1 ? 3 : (deg <= 8 ? 4 : 3);
+    return order >= 2 ? 2 : order == 1 ? (deg <= 3 ? 4 : 3) : (deg <= 8 ? 4 : 3);
 }
 __host__ __device__ constexpr int fwd_edge_unroll(int deg, int order) { return order >= 2 && deg > 8 ? 1 : 3; }
 
