@@ -174,15 +174,17 @@ def bench_adjoint(args, sb, W, torch, dev):
 
 
 def bench_operators(args, sb, torch, dev, wl, px, py, tri, nodal, off, idx, fwd_ms):
-    """SPH operators (Sec. 2) on the headline workload: difference gradient
-    (per-pair pre-weights), divergence and curl (two fields, one pass) and the
-    boundary normal, each against the forward pair kernel on the same pairs."""
+    """SPH operators (Sec. 2) on the headline workload: difference and
+    symmetric gradients, divergence and curl (two fields, one pass), the
+    boundary normal and the contact pressure term (App. A), each against the
+    forward pair kernel on the same pairs."""
     P, N = int(idx.numel()), wl.n_particles
     g = torch.Generator(device=dev).manual_seed(5)
     rho = 1000.0 + 100.0 * torch.rand(nodal.shape, dtype=torch.float64, device=dev, generator=g)
     ay = torch.randn(nodal.shape, dtype=torch.float64, device=dev, generator=g)
     ap = torch.randn(N, dtype=torch.float64, device=dev, generator=g)
     rp = 1000.0 + 100.0 * torch.rand(N, dtype=torch.float64, device=dev, generator=g)
+    p_pair = 1.0e3 * torch.rand(P, dtype=torch.float64, device=dev, generator=g)
     steps = max(3, args.steps // 2)
     out = {}
     cases = (("difference_gradient", lambda: sb.gradient_difference(wl.kernel, wl.h, px, py, ap, rp, tri, nodal, rho,
@@ -190,7 +192,9 @@ def bench_operators(args, sb, torch, dev, wl, px, py, tri, nodal, off, idx, fwd_
              ("symmetric_gradient", lambda: sb.gradient_symmetric(wl.kernel, wl.h, px, py, ap, rp, tri, nodal, rho,
                                                                   off, idx)),
              ("divergence_curl", lambda: sb.divergence_curl(wl.kernel, wl.h, px, py, tri, nodal, ay, off, idx)),
-             ("boundary_normal", lambda: sb.boundary_normal(wl.kernel, wl.h, px, py, tri, off, idx)))
+             ("boundary_normal", lambda: sb.boundary_normal(wl.kernel, wl.h, px, py, tri, off, idx)),
+             ("pressure_contact", lambda: sb.pressure_contact(wl.kernel, wl.h, 1000.0, px, py, ap, rp, tri, off, idx,
+                                                              p_pair)))
     for name, fn in cases:
         ms = event_time(torch, fn, steps, 2)
         out[name] = {"ms": ms, "pairs_per_s": P / (ms * 1e-3), "over_forward_kernel": ms / fwd_ms}

@@ -231,6 +231,24 @@ int sphbi_operator(const sphbi_kernel *kernel /* host */, const sphbi_opts *opts
                    double *out_b, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Boundary pressure acceleration with one pressure value per contact
+ * (App. A, the second choice for the boundary pressure): for every particle
+ *   a_i = - sum over its pairs q of rho0 (p_q / rho0^2 + p_i / rho_i^2) int_T grad W,
+ * with rho0 the (constant) rest density of the boundary, p_q the pressure at
+ * the particle's closest point on the pair's triangle, one value per pair in
+ * the order of tri_idx (the caller evaluates it, e.g. by MLS), and p_i, rho_i
+ * the particle's pressure and density [N].  Output (ax, ay) [N].  The
+ * per-vertex variant of App. A is minus the symmetric gradient of
+ * sphbi_operator with rho = rho0 at the nodes, divided by rho_i.
+ * ws: sphbi_operator_workspace(N, T) bytes.  FP64 only.  Asynchronous.
+ * ------------------------------------------------------------------- */
+int sphbi_pressure_contact(const sphbi_kernel *kernel /* host */, const sphbi_opts *opts /* host, NULL = default */,
+                           double h, double rho0, int64_t N, const double *px, const double *py,
+                           const double *p_particle, const double *rho_particle, int64_t T, const double *tri,
+                           const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, const double *p_pair,
+                           double *ax, double *ay, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------
  * Learned surrogate of the per-pair result (an extension; the paper has no
  * learned part).  A network 8 -> 128 -> 128 -> 128 -> 4 maps the
  * canonical features of a pair to the standardised (I, h Gx, h Gy) of a unit

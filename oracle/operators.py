@@ -16,6 +16,8 @@ Each operator is taken the way the paper states it, in plain steps:
 * Divergence and curl (the equation after eq. improper) from the gradient
   integrals of the two components.
 * Boundary normal (App. A): int grad W of the unit field.
+* Boundary pressure with one pressure value per contact (App. A): each
+  pair's field is the constant rho0 (p_q / rho0^2 + p_i / rho_i^2).
 
 Reading of the symmetric form: eq. intsphdiffops writes the bracket with a
 plus (rho [<grad(A/rho)> + A/rho^2 <grad rho>]) and its integral with a
@@ -89,3 +91,14 @@ def boundary_normal(kernel_id, h, px, py, tri, offsets, tri_idx, nthreads=0):
     _, nx, ny = integrate(kernel_id, h, px, py, tri, np.ones((1, tri.shape[1])), offsets, tri_idx,
                           nthreads=nthreads)
     return nx, ny
+
+
+def pressure_contact(kernel_id, h, rho0, px, py, p_particle, rho_particle, tri, offsets, tri_idx, p_pair,
+                     nthreads=0):
+    """Boundary pressure acceleration with one pressure value per contact (App. A, second choice):
+    a_i = - sum_q rho0 (p_q / rho0^2 + p_i / rho_i^2) int_T grad W, the field of pair q constant."""
+    own = _owners(offsets)
+    p_particle, rho_particle = np.asarray(p_particle, float), np.asarray(rho_particle, float)
+    f = rho0 * (np.asarray(p_pair, float) / rho0 ** 2 + (p_particle / rho_particle ** 2)[own])
+    gx, gy = _pair_gradient(kernel_id, h, px, py, tri, f[None, :], offsets, tri_idx, nthreads)
+    return -gx, -gy

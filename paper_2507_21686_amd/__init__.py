@@ -84,6 +84,8 @@ def lib():
         L.sphbi_operator_workspace.restype = C.c_size_t
         L.sphbi_operator.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), i32, d, i32, i64, vp, vp, vp,
                                      vp, i64, vp, vp, vp, vp, vp, i64, vp, vp, vp, C.c_size_t, vp]
+        L.sphbi_pressure_contact.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, d, i64, vp, vp, vp, vp,
+                                             i64, vp, vp, vp, i64, vp, vp, vp, vp, C.c_size_t, vp]
         f = C.c_float
         L.sphbi_surrogate_features.argtypes = [d, i64, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
         L.sphbi_surrogate_targets.argtypes = [i64, d, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
@@ -332,6 +334,29 @@ def divergence_curl(kernel, h, px, py, tri, Ax, Ay, offsets, tri_idx):
 def boundary_normal(kernel, h, px, py, tri, offsets, tri_idx):
     """int grad W over the boundary, per particle (App. A)."""
     return operator(OP_NORMAL, kernel, h, px, py, tri, offsets, tri_idx)
+
+
+def pressure_contact(kernel, h, rho0, px, py, p_particle, rho_particle, tri, offsets, tri_idx, p_pair, ws=None):
+    """Boundary pressure acceleration (ax, ay) [N] with one pressure per contact (App. A):
+    -sum_q rho0 (p_q/rho0^2 + p_i/rho_i^2) int_T grad W; p_pair [n_pairs] in tri_idx order."""
+    k = kernel_preset(kernel) if isinstance(kernel, int) else kernel
+    px, py, tri = _dev(px), _dev(py), _dev(tri)
+    p_particle, rho_particle, p_pair = _dev(p_particle), _dev(rho_particle), _dev(p_pair)
+    offsets, tri_idx = _dev(offsets, torch.int64), _dev(tri_idx, torch.int32)
+    N, T, P = px.numel(), tri.shape[1], tri_idx.numel()
+    if p_pair.numel() != P or p_particle.numel() != N or rho_particle.numel() != N:
+        raise SphbiError("p_pair must be [n_pairs], p_particle and rho_particle [N]")
+    ax = torch.empty(N, dtype=torch.float64, device=px.device)
+    ay = torch.empty_like(ax)
+    need = int(lib().sphbi_operator_workspace(N, T))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=px.device)
+    o = opts(FP64)
+    _check(lib().sphbi_pressure_contact(C.byref(k), C.byref(o), float(h), float(rho0), N, _ptr(px), _ptr(py),
+                                        _ptr(p_particle), _ptr(rho_particle), T, _ptr(tri), _ptr(offsets),
+                                        _ptr(tri_idx), P, _ptr(p_pair), _ptr(ax), _ptr(ay), _ptr(ws), ws.numel(),
+                                        _stream()), "sphbi_pressure_contact")
+    return ax, ay
 
 
 # ----------------------------------------------------------------------------

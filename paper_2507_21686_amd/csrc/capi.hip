@@ -604,6 +604,34 @@ int sphbi_operator(const sphbi_kernel *kernel, const sphbi_opts *opts, int32_t o
                            out_b, ws, (hipStream_t)stream);
 }
 
+int sphbi_pressure_contact(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, double rho0, int64_t N,
+                           const double *px, const double *py, const double *p_particle,
+                           const double *rho_particle, int64_t T, const double *tri, const int64_t *offsets,
+                           const int32_t *tri_idx, int64_t n_pairs, const double *p_pair, double *ax, double *ay,
+                           void *ws, size_t ws_bytes, void *stream) {
+    sphbi_opts o;
+    int rc = check_common(kernel, opts, &o, h, 1, N, T, n_pairs);
+    if (rc) return rc;
+    if (o.precision != SPHBI_FP64) { set_error("the pressure term runs in FP64 only"); return SPHBI_EUNSUPPORTED; }
+    if (!(rho0 != 0.0) || !isfinite(rho0)) { set_error("rho0 must be finite and non-zero"); return SPHBI_EINVAL; }
+    if (N > 0 && (!px || !py || !offsets || !p_particle || !rho_particle || !ax || !ay)) {
+        set_error("particle arrays are NULL");
+        return SPHBI_EINVAL;
+    }
+    if (n_pairs > 0 && (!tri_idx || !p_pair)) { set_error("pair arrays are NULL"); return SPHBI_EINVAL; }
+    if (T > 0 && !tri) { set_error("triangle array is NULL"); return SPHBI_EINVAL; }
+    const void *ptrs[] = {px, py, p_particle, rho_particle, tri, offsets, tri_idx, p_pair, ax, ay, ws};
+    for (const void *p : ptrs)
+        if (!aligned8(p)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
+    if (N == 0) return SPHBI_OK;
+    const size_t need = operator_workspace(N, T);
+    if (!ws || ws_bytes < need) { set_error("workspace too small (%zu < %zu)", ws_bytes, need); return SPHBI_ENOWORKSPACE; }
+    int deg = 0;
+    const KArgs K = make_kargs(kernel, &deg);
+    return launch_pressure_contact(deg, K, h, rho0, N, px, py, p_particle, rho_particle, offsets, tri_idx, n_pairs, T,
+                                   tri, p_pair, ax, ay, ws, (hipStream_t)stream);
+}
+
 // ----------------------------------------------------------------------------
 // learned surrogate
 // ----------------------------------------------------------------------------

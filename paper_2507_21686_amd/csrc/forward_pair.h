@@ -49,7 +49,9 @@
 //                 coefficients, then beta_T), formed in the pair's registers
 //                 before the evaluation: (I, Gx, Gy) of the combination;
 //   kFieldDivCurl the record's field as A_x and rec2's as A_y, both through
-//                 one closed-form pass: (0, div, curl).
+//                 one closed-form pass: (0, div, curl);
+//   kFieldPairWeight the record's field, each pair's result times
+//                 rec2[q] + gam[particle] (rec2 is then one value per pair).
 //
 // This header is included by forward.hip (plain fields) and operators.hip
 // (the other modes); the anonymous namespace keeps each unit's
@@ -65,7 +67,7 @@
 namespace sphbi {
 namespace {
 
-constexpr int kFieldPlain = 0, kFieldComb = 1, kFieldDivCurl = 2;
+constexpr int kFieldPlain = 0, kFieldComb = 1, kFieldDivCurl = 2, kFieldPairWeight = 3;
 
 // The pair's record with the combined field: coefficients e + s e2,
 // s = rec2[10] - g.
@@ -345,6 +347,12 @@ __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_wav
                                                                             vY);
                         else pair_fwd_rot<DEG, ORDER, double, ExactMath, EU>(K, ExactMath(), 0.0, px[ip], py[ip], invh,
                                                                              r, key & 3, vI, vX, vY);
+                        if constexpr (FM == kFieldPairWeight) {
+                            const double m = rec2[q] + gam[ip];
+                            vI *= m;
+                            vX *= m;
+                            vY *= m;
+                        }
                     }
                 }
                 if (per_pair) {
@@ -402,7 +410,7 @@ template <int DEG, int ORDER, bool MIXED, int FM>
 void launch_fwd_t(const KArgs &K, const FwdArgs &a, hipStream_t s) {
     const int64_t waves = (a.N + 63) / 64;
     constexpr int SW = ORDER >= 2 ? 512 : 256;     // LDS: 14 or 7 KB per one-wave block
-    if constexpr (fwd_sorted(DEG, ORDER) || FM == kFieldDivCurl)
+    if constexpr (fwd_sorted(DEG, ORDER) || FM == kFieldDivCurl || FM == kFieldPairWeight)
         hipLaunchKernelGGL((forward_sorted_kernel<DEG, ORDER, MIXED, SW, FM>), dim3((unsigned)waves), dim3(64), 0,
                            s, K, a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair,
                            a.P, a.T, a.rec2, a.gam);

@@ -59,6 +59,11 @@ int launch_operator(int op, int order, int deg, const KArgs &K, double h, int64_
                     const double *py, const double *qa, const double *qb, const int64_t *off, const int32_t *tri_idx,
                     int64_t P, int64_t T, const double *tri, const double *fa, const double *fb, double *out_a,
                     double *out_b, void *ws, hipStream_t s);
+// boundary pressure with one pressure value per contact; ws as for the operators
+int launch_pressure_contact(int deg, const KArgs &K, double h, double rho0, int64_t N, const double *px,
+                            const double *py, const double *p_i, const double *rho_i, const int64_t *off,
+                            const int32_t *tri_idx, int64_t P, int64_t T, const double *tri, const double *p_pair,
+                            double *ax, double *ay, void *ws, hipStream_t s);
 // the adjoint pair kernel for linear fields (its own translation unit)
 void launch_adjoint_linear(int deg, const KArgs &K, double invh, int64_t N, const double *px, const double *py,
                            const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,

@@ -29,6 +29,13 @@
 // Boundary normal (App. A): n(x) = int grad W, the forward kernel on records
 // of the unit field.
 //
+// Boundary pressure with one pressure value per contact (App. A, second
+// choice): a_i = - sum_q rho0 (p_q / rho0^2 + p_i / rho_i^2) int_T grad W, with
+// p_q the pressure at the particle's closest point on the pair's triangle.
+// The records hold the constant field -1/rho0 and each pair's result is
+// scaled by p_q + rho0^2 p_i / rho_i^2 in the forward kernel
+// (kFieldPairWeight).
+//
 // FP64 throughout; per-particle sums in pair order (deterministic).
 
 #include <math.h>
@@ -41,6 +48,7 @@ namespace {
 // op codes shared with the C-ABI
 constexpr int kDiff = SPHBI_OP_GRAD_DIFFERENCE, kSym = SPHBI_OP_GRAD_SYMMETRIC, kDivCurl = SPHBI_OP_DIV_CURL,
               kNormal = SPHBI_OP_NORMAL;
+constexpr int kContact = 100;               // internal: the contact pressure term
 
 // Per-triangle records: rec = vertices and the coefficients of F1 (the
 // layout of the forward records), rec2 = the coefficients of F2, then
@@ -49,7 +57,7 @@ constexpr int kDiff = SPHBI_OP_GRAD_DIFFERENCE, kSym = SPHBI_OP_GRAD_SYMMETRIC, 
 template <int ORDER>
 __global__ __launch_bounds__(256) void op_prepare_kernel(int op, int64_t T, const double *__restrict__ tri,
                                                          const double *__restrict__ fa, const double *__restrict__ fb,
-                                                         double invh, double *__restrict__ rec,
+                                                         double invh, double unit, double *__restrict__ rec,
                                                          double *__restrict__ rec2) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
@@ -60,8 +68,8 @@ __global__ __launch_bounds__(256) void op_prepare_kernel(int op, int64_t T, cons
 #pragma unroll
     for (int k = 0; k < 10; ++k) A[k] = B[k] = 0.0;
     double beta = 0.0;
-    if (op == kNormal) {
-        A[0] = 1.0;
+    if (op == kNormal || op == kContact) {
+        A[0] = unit;
     } else {
 #pragma unroll
         for (int k = 0; k < NN; ++k) {
@@ -93,12 +101,13 @@ __global__ __launch_bounds__(256) void op_prepare_kernel(int op, int64_t T, cons
     for (int k = 11; k < kRecDoubles; ++k) o2[k] = 0.0;
 }
 
-// gam(x) of the combined field
+// gam(x): of the combined field, or the particle's part of the contact
+// pressure weight
 __global__ void op_gamma_kernel(int op, int64_t N, const double *__restrict__ qa, const double *__restrict__ qb,
-                                double *__restrict__ gam) {
+                                double rho0, double *__restrict__ gam) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    gam[i] = op == kDiff ? qa[i] : -qa[i] / (qb[i] * qb[i]);
+    gam[i] = op == kDiff ? qa[i] : (op == kContact ? rho0 * rho0 * qa[i] / (qb[i] * qb[i]) : -qa[i] / (qb[i] * qb[i]));
 }
 
 // the per-particle factor of the gradient forms: 1/rho(x) or rho(x)
@@ -138,9 +147,9 @@ int launch_operator(int op, int order, int deg, const KArgs &K, double h, int64_
     if (op == kNormal) order = 0;
     if (T > 0) {
         const unsigned tb = (unsigned)((T + 255) / 256);
-        if (order == 0) hipLaunchKernelGGL(op_prepare_kernel<0>, dim3(tb), dim3(256), 0, s, op, T, tri, fa, fb, invh, rec, rec2);
-        else if (order == 1) hipLaunchKernelGGL(op_prepare_kernel<1>, dim3(tb), dim3(256), 0, s, op, T, tri, fa, fb, invh, rec, rec2);
-        else hipLaunchKernelGGL(op_prepare_kernel<3>, dim3(tb), dim3(256), 0, s, op, T, tri, fa, fb, invh, rec, rec2);
+        if (order == 0) hipLaunchKernelGGL(op_prepare_kernel<0>, dim3(tb), dim3(256), 0, s, op, T, tri, fa, fb, invh, 1.0, rec, rec2);
+        else if (order == 1) hipLaunchKernelGGL(op_prepare_kernel<1>, dim3(tb), dim3(256), 0, s, op, T, tri, fa, fb, invh, 1.0, rec, rec2);
+        else hipLaunchKernelGGL(op_prepare_kernel<3>, dim3(tb), dim3(256), 0, s, op, T, tri, fa, fb, invh, 1.0, rec, rec2);
     }
     const unsigned nb = (unsigned)((N + 255) / 256);
     if (op == kNormal) {
@@ -153,7 +162,7 @@ int launch_operator(int op, int order, int deg, const KArgs &K, double h, int64_
         else if (order == 1) launch_fwd_deg<1, false, kFieldDivCurl>(deg, K, a, s);
         else launch_fwd_deg<3, false, kFieldDivCurl>(deg, K, a, s);
     } else {
-        hipLaunchKernelGGL(op_gamma_kernel, dim3(nb), dim3(256), 0, s, op, N, qa, qb, gam);
+        hipLaunchKernelGGL(op_gamma_kernel, dim3(nb), dim3(256), 0, s, op, N, qa, qb, 0.0, gam);
         const FwdArgs a{0.0, invh, N, px, py, off, tri_idx, rec, Ib, out_a, out_b, nullptr, P, T, rec2, gam};
         if (order == 0) launch_fwd_deg<0, false, kFieldComb>(deg, K, a, s);
         else if (order == 1) launch_fwd_deg<1, false, kFieldComb>(deg, K, a, s);
@@ -162,6 +171,38 @@ int launch_operator(int op, int order, int deg, const KArgs &K, double h, int64_
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("operator launch: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
+    return SPHBI_OK;
+}
+
+}  // namespace sphbi
+
+namespace sphbi {
+
+int launch_pressure_contact(int deg, const KArgs &K, double h, double rho0, int64_t N, const double *px,
+                            const double *py, const double *p_i, const double *rho_i, const int64_t *off,
+                            const int32_t *tri_idx, int64_t P, int64_t T, const double *tri, const double *p_pair,
+                            double *ax, double *ay, void *ws, hipStream_t s) {
+    if (N == 0) return SPHBI_OK;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t Tn = (size_t)(T > 0 ? T : 1), Nn = (size_t)(N > 0 ? N : 1);
+    char *w = (char *)ws;
+    double *rec = (double *)w;
+    w += al(Tn * kRecDoubles * sizeof(double));
+    double *rec2 = (double *)w;                 // written by the preparation, not read
+    w += al(Tn * kRecDoubles * sizeof(double));
+    double *gam = (double *)w;
+    w += al(Nn * sizeof(double));
+    double *Ib = (double *)w;
+    const double invh = 1.0 / h;
+    if (T > 0)
+        hipLaunchKernelGGL(op_prepare_kernel<0>, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, kContact, T, tri,
+                           nullptr, nullptr, invh, -1.0 / rho0, rec, rec2);
+    hipLaunchKernelGGL(op_gamma_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, kContact, N, p_i, rho_i,
+                       rho0, gam);
+    const FwdArgs a{0.0, invh, N, px, py, off, tri_idx, rec, Ib, ax, ay, nullptr, P, T, p_pair, gam};
+    launch_fwd_deg<0, false, kFieldPairWeight>(deg, K, a, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_error("pressure launch: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
     return SPHBI_OK;
 }
 

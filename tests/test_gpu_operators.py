@@ -258,3 +258,56 @@ def test_operator_deterministic():
         a = gpu_op(op, wl, off, idx, A, rho, Ay, Ap, rp)
         b = gpu_op(op, wl, off, idx, A, rho, Ay, Ap, rp)
         assert all(np.array_equal(x, y) for x, y in zip(a, b)), OPS[op]
+
+
+@pytest.mark.parametrize("kid", [0, 1, 2, 3])
+@pytest.mark.parametrize("case", ["covering", "band"])
+def test_pressure_contact_parity(kid, case):
+    """Boundary pressure with one pressure per contact (App. A) against the oracle."""
+    wl = (W.covering_workload(n_side=48, nx=6, ny=12, seed=21 + kid, kernel=kid, field_order=0) if case == "covering"
+          else W.band_wall(seed=3))
+    say(f"pressure contact {case} kernel={kid}")
+    off, idx = oracle.pairlist(wl.px, wl.py, wl.tri, wl.h, nthreads=NTH)
+    rng = np.random.default_rng(40 + kid)
+    rho0 = 1000.0
+    p_pair = rng.uniform(0.0, 5.0e3, len(idx))
+    p_i, rho_i = rng.uniform(-1.0e3, 5.0e3, wl.n_particles), rng.uniform(950.0, 1050.0, wl.n_particles)
+    got = sb.pressure_contact(kid, wl.h, rho0, dev(wl.px), dev(wl.py), dev(p_i), dev(rho_i), dev(wl.tri),
+                              dev(off, torch.int64), dev(idx, torch.int32), dev(p_pair))
+    torch.cuda.synchronize()
+    got = [g.cpu().numpy() for g in got]
+    ref = O.pressure_contact(kid, wl.h, rho0, wl.px, wl.py, p_i, rho_i, wl.tri, off, idx, p_pair, nthreads=NTH)
+    amax = rho0 * (p_pair.max() / rho0 ** 2 + np.abs(p_i / rho_i ** 2).max())
+    scale = metrics.grad_scale(kid, wl.h) * amax
+    err = max(float(metrics.scaled_err(g, r, scale).max(initial=0.0)) for g, r in zip(got, ref))
+    say(f"  pairs={len(idx)} err={err:.2e}")
+    assert err <= TOL[kid]
+
+
+def test_pressure_contact_edge_cases():
+    say("pressure contact edge cases")
+    wl = W.covering_workload(n_side=16, nx=2, ny=4, seed=3, kernel=0, field_order=0)
+    off, idx = oracle.pairlist(wl.px, wl.py, wl.tri, wl.h)
+    rng = np.random.default_rng(2)
+    p_pair = rng.uniform(0.0, 1.0, len(idx))
+    p_i, rho_i = rng.uniform(0.0, 1.0, wl.n_particles), rng.uniform(0.9, 1.1, wl.n_particles)
+    args = lambda o, i, pp: sb.pressure_contact(0, wl.h, 1.0, dev(wl.px), dev(wl.py), dev(p_i), dev(rho_i),
+                                                dev(wl.tri), dev(o, torch.int64), dev(i, torch.int32), dev(pp))
+    ref = [g.cpu().numpy() for g in args(off, idx, p_pair)]
+    # an invalid triangle index per particle (its pressure arbitrary) contributes nothing
+    off2 = off + np.arange(len(off))
+    idx2 = np.empty(len(idx) + wl.n_particles, np.int32)
+    pp2 = np.empty(len(idx) + wl.n_particles)
+    for i in range(wl.n_particles):
+        idx2[off2[i]:off2[i + 1] - 1] = idx[off[i]:off[i + 1]]
+        pp2[off2[i]:off2[i + 1] - 1] = p_pair[off[i]:off[i + 1]]
+        idx2[off2[i + 1] - 1] = -1 if i % 2 else wl.n_triangles
+        pp2[off2[i + 1] - 1] = 1e30
+    got = [g.cpu().numpy() for g in args(off2, idx2, pp2)]
+    assert all(np.array_equal(g, r) for g, r in zip(got, ref))
+    # no pairs: zero acceleration
+    z = [g.cpu().numpy() for g in args(np.zeros(wl.n_particles + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))]
+    assert np.all(z[0] == 0.0) and np.all(z[1] == 0.0)
+    with pytest.raises(sb.SphbiError):
+        sb.pressure_contact(0, wl.h, 0.0, dev(wl.px), dev(wl.py), dev(p_i), dev(rho_i), dev(wl.tri),
+                            dev(off, torch.int64), dev(idx, torch.int32), dev(p_pair))

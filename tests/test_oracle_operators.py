@@ -146,3 +146,38 @@ def test_out_of_range_pairs_contribute_nothing():
         idx2[off2[i + 1] - 1] = tri.shape[1] + 5 if i % 2 else -1
     got = O.gradient_difference(0, H, px, py, Ap, rp, tri, A, rho, off2, idx2)
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+@pytest.mark.parametrize("kid", [0, 1, 2, 3])
+def test_contact_pressure_wall_and_full_support(kid):
+    """App. A, one pressure per contact: at a straight wall with constant
+    contact pressure P0 the acceleration is -rho0 (P0/rho0^2 + p_i/rho_i^2) n,
+    n = (0, -int_line W ds); with full support it vanishes."""
+    d = [0.1 * H, 0.45 * H, 0.8 * H]
+    tri, px, py, off, idx = wall_case(d)
+    rho0, P0 = 1000.0, 2.5e3
+    p_i, rho_i = np.array([1.0e3, 4.0e3, -2.0e2]), np.array([990.0, 1010.0, 1000.0])
+    ax, ay = O.pressure_contact(kid, H, rho0, px, py, p_i, rho_i, tri, off, idx, np.full(len(idx), P0))
+    ref = np.array([line_integral_of_W(kid, H, di) for di in d])
+    want = rho0 * (P0 / rho0 ** 2 + p_i / rho_i ** 2) * ref          # -(...) * (0, -L)
+    scale = np.abs(want).max()
+    assert np.abs(ax).max() < 1e-12 * scale
+    assert np.abs(ay - want).max() < 1e-11 * scale
+    tri, px, py, off, idx = full_support_case(seed=30 + kid, n=6)
+    ax, ay = O.pressure_contact(kid, H, rho0, px, py, np.full(6, 3.0e3), np.full(6, 1000.0), tri, off, idx,
+                                np.full(len(idx), P0))
+    assert np.abs(ax).max() < 1e-13 / H * 10 and np.abs(ay).max() < 1e-13 / H * 10
+
+
+def test_contact_pressure_matches_per_vertex_form_for_constant_pressure():
+    """With the same constant pressure at every contact and every vertex the
+    two boundary pressure choices of App. A agree: the per-vertex one is minus
+    the symmetric gradient (rho = rho0 at the nodes) divided by rho_i."""
+    tri, px, py, off, idx = wall_case([0.2 * H, 0.6 * H])
+    rho0, P0 = 1000.0, 1.7e3
+    p_i, rho_i = np.array([900.0, 1.2e3]), np.array([1005.0, 995.0])
+    ax, ay = O.pressure_contact(1, H, rho0, px, py, p_i, rho_i, tri, off, idx, np.full(len(idx), P0))
+    A = np.full((3, tri.shape[1]), P0)
+    gx, gy = O.gradient_symmetric(1, H, px, py, p_i, rho_i, tri, A, np.full_like(A, rho0), off, idx)
+    assert np.allclose(ax, -gx / rho_i, rtol=1e-13, atol=1e-13 * np.abs(gy).max())
+    assert np.allclose(ay, -gy / rho_i, rtol=1e-13, atol=1e-13 * np.abs(gy).max())
