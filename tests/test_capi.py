@@ -112,3 +112,25 @@ def test_operator_arguments_rejected_without_device():
     # N = 0 is a no-op
     assert L.sphbi_operator(C.byref(k), C.byref(o), 0, 1.0, 3, 0, z, z, z, z, 0, z, z, z, z, z, 0, z, z, z, 0,
                             z) == 0
+
+
+def test_pressure_contact_arguments_rejected_without_device():
+    """sphbi_pressure_contact validates before any launch."""
+    import numpy as np
+    L = sb.lib()
+    k = sb.kernel_preset(0)
+    o = sb.opts()
+    z = C.c_void_p(None)
+    N, T = 4, 2
+    host = np.zeros(64, dtype=np.float64)            # stand-in pointers: never dereferenced on these paths
+    p = C.c_void_p(host.ctypes.data)
+    need = int(L.sphbi_operator_workspace(N, T))
+
+    def call(rho0=1000.0, opts=o, p_pair=p, ws_bytes=need):
+        return L.sphbi_pressure_contact(C.byref(k), C.byref(opts), 1.0, rho0, N, p, p, p, p, T, p, p, p, 8, p_pair,
+                                        p, p, p, ws_bytes, z)
+
+    assert call(rho0=0.0) == -1 and b"rho0" in L.sphbi_last_error()
+    assert call(opts=sb.opts(sb.MIXED)) == -2
+    assert call(p_pair=z) == -1
+    assert call(ws_bytes=need - 8) == -4
