@@ -12,7 +12,9 @@ records + pair kernel, FP64).  The pair list is built once beforehand and
 timed separately.  The JSON line also carries the dominant kernel's roofline
 position, the CPU oracle timed on a bounded sample and, under "modes":
 the same step in the mixed FP32/FP64 precision mode with its largest
-scale-normalised deviation from the FP64 results; the adjoint on the
+scale-normalised deviation from the FP64 results; the SPH operators; the
+quadrature comparison (collapsed Gauss-Legendre rules of 4..32 points per
+direction, time and error against the closed form); the adjoint on the
 differentiation workload (262,144 particles, Wendland C4, P3); and the
 learned surrogate, trained here on the GPU, against the closed form on fresh
 pairs at a stated error.
@@ -271,6 +273,64 @@ def bench_surrogate(args, sb, torch, dev):
 
 
 # ----------------------------------------------------------------------------
+def bench_quadrature(args, sb, W, torch, dev, wl, px, py, tri, nodal, off, idx, ref, fwd_ms):
+    """Quadrature of the same sums (Sec. 6.1-6.2): n x n collapsed Gauss-Legendre
+    points per pair, time and scale-normalised error against the FP64 closed
+    form.  On the headline workload every triangle is larger than the support
+    and no rule of this size resolves the cut-off.  On a mesh of triangles
+    smaller than h (65,536 particles, 262,144 triangles about h/2 across), the
+    pairs whose triangle lies wholly inside the support are timed on their
+    own: there the integrand is smooth and a rule is the paper's suggested
+    hybrid (Sec. 6.1)."""
+
+    def err(out, want, kernel, h, nod):
+        amax = float(torch.abs(nod).max()) * 3.0
+        sG = 2 * kernel_c_d_int_k(sb, kernel) / h * amax
+        e = [float((torch.abs(out[0] - want[0]) / torch.clamp(torch.abs(want[0]), min=amax)).max())]
+        e += [float((torch.abs(out[k] - want[k]) / torch.clamp(torch.abs(want[k]), min=sG)).max()) for k in (1, 2)]
+        return {"I": e[0], "G": max(e[1], e[2])}
+
+    def run(w, x, y, tr, nod, o, i, want, base_ms, label, ns):
+        rows, p = {}, int(i.numel())
+        for n in ns:
+            fn = lambda: sb.integrate_quadrature(w.kernel, w.h, x, y, tr, nod, o, i, n)
+            out = fn()
+            ms = event_time(torch, fn, 3, 1)
+            e = err(out, want, w.kernel, w.h, nod)
+            rows[str(n)] = {"ms": ms, "pairs_per_s": p / (ms * 1e-3), "over_closed_form": ms / base_ms,
+                            "max_scaled_err": e}
+            log(f"bench: quadrature {label} n={n}: {ms:.3f} ms ({ms / base_ms:.2f}x closed form), "
+                f"err I {e['I']:.1e} G {e['G']:.1e}")
+        return rows
+
+    out = {"headline_all_pairs": run(wl, px, py, tri, nodal, off, idx, ref, fwd_ms, "headline", (4, 8, 16, 32))}
+    fine = W.covering_workload(n_side=256, nx=256, ny=512, seed=3)
+    x, y, tr, nod = (torch.tensor(a, device=dev) for a in (fine.px, fine.py, fine.tri, fine.nodal))
+    o, i = sb.pairlist(x, y, tr, fine.h)
+    P, N = int(i.numel()), fine.n_particles
+    own = torch.repeat_interleave(torch.arange(N, device=dev), o[1:] - o[:-1])
+    t = i.long()
+    inside = torch.ones(P, dtype=torch.bool, device=dev)
+    for v in range(3):
+        dx, dy = tr[2 * v][t] - x[own], tr[2 * v + 1][t] - y[own]
+        inside &= dx * dx + dy * dy < fine.h * fine.h
+    cnt = torch.bincount(own[inside], minlength=N)
+    o_in = torch.cat([torch.zeros(1, dtype=torch.int64, device=dev), torch.cumsum(cnt, 0)])
+    i_in = i[inside].contiguous()
+    P_in = int(i_in.numel())
+    cf = sb.integrate(fine.kernel, fine.h, x, y, tr, nod, o_in, i_in)
+    cf_ms = event_time(torch, lambda: sb.integrate(fine.kernel, fine.h, x, y, tr, nod, o_in, i_in), 3, 1)
+    log(f"bench: small triangles: {P_in} of {P} pairs ({P_in / P:.1%}) have the triangle inside the support; "
+        f"closed form on them {cf_ms:.3f} ms")
+    out["small_triangles_inside_support"] = {
+        "pairs": P_in, "of_pairs": P, "closed_form_ms": cf_ms,
+        "rule": run(fine, x, y, tr, nod, o_in, i_in, cf, cf_ms, "inside support", (2, 3, 4, 6, 8))}
+    out["workload"] = ("headline: the headline workload's pairs; small triangles: 65,536 particles, 262,144 "
+                       "triangles (~h/2 across), pairs with all three vertices within h; P3, Wendland C2, FP64; "
+                       "closed-form times include the field preparation")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +343,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the surrogate")
     ap.add_argument("--no-operators", action="store_true", help="skip timing the SPH operators")
+    ap.add_argument("--no-quadrature", action="store_true", help="skip the quadrature comparison")
     ap.add_argument("--surrogate-steps", type=int, default=40000, help="Adam steps of the surrogate training")
     ap.add_argument("--surrogate-level", type=float, default=1e-2,
                     help="scale-normalised per-pair error the router is calibrated to")
@@ -413,6 +474,9 @@ def main():
     if not args.no_operators:
         result["modes"]["operators"] = bench_operators(args, sb, torch, dev, wl, px, py, tri, nodal, off, idx,
                                                        kern_avg)
+    if not args.no_quadrature:
+        result["modes"]["quadrature"] = bench_quadrature(args, sb, W, torch, dev, wl, px, py, tri, nodal, off, idx,
+                                                         out64, ms_step)
     if not args.no_adjoint:
         result["modes"]["adjoint"] = bench_adjoint(args, sb, W, torch, dev)
     if not args.no_surrogate:

@@ -168,6 +168,27 @@ int sphbi_integrate_prepared(const sphbi_kernel *kernel /* host */, const sphbi_
                              double *I, double *Gx, double *Gy, double *per_pair, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Numerical quadrature of the same sums as sphbi_integrate (the comparison
+ * of the closed form with quadrature rules, Sec. 6.1-6.2).
+ *
+ * Every pair's triangle is integrated with a collapsed (Duffy) tensor
+ * Gauss-Legendre rule of n_gauss x n_gauss points: barycentric L1 = u,
+ * L2 = (1 - u) v, area element |2 area| (1 - u) du dv; exact for the field
+ * times polynomials of total degree <= 2 n_gauss - 2, but the kernel's
+ * compact cut-off and its odd powers of |x - x'| are not polynomials, which
+ * limits the accuracy (Sec. 6.1).  Arguments, layouts and outputs as
+ * sphbi_integrate (I, Gx, Gy [N], world units, the gradient with its 1/h);
+ * 1 <= n_gauss <= SPHBI_MAX_GAUSS, else SPHBI_EINVAL.  FP64, no workspace,
+ * deterministic (pairs summed in order).  Asynchronous.
+ * ------------------------------------------------------------------- */
+#define SPHBI_MAX_GAUSS 64
+
+int sphbi_integrate_quadrature(const sphbi_kernel *kernel /* host */, double h, int32_t n_nodes, int32_t n_gauss,
+                               int64_t N, const double *px, const double *py, int64_t T, const double *tri,
+                               const double *nodal, const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs,
+                               double *I, double *Gx, double *Gy, void *stream);
+
+/* ---------------------------------------------------------------------
  * Adjoint (vector-Jacobian product) of sphbi_integrate.
  *
  * Given cotangents gI, gGx, gGy [N] of the per-particle outputs, writes the

@@ -26,7 +26,8 @@ EXPORTS = ["sphbi_kernel_preset", "sphbi_default_opts", "sphbi_last_error", "sph
            "sphbi_field_prepare", "sphbi_integrate_prepared", "sphbi_integrate_backward_workspace",
            "sphbi_integrate_backward", "sphbi_surrogate_features", "sphbi_surrogate_targets", "sphbi_mlp_workspace", "sphbi_mlp_forward",
            "sphbi_mlp_loss_grad", "sphbi_adam_step", "sphbi_surrogate_model_bytes", "sphbi_surrogate_pack",
-           "sphbi_surrogate_workspace", "sphbi_surrogate_integrate"]
+           "sphbi_surrogate_workspace", "sphbi_surrogate_integrate", "sphbi_operator_workspace", "sphbi_operator",
+           "sphbi_pressure_contact", "sphbi_integrate_quadrature"]
 MLP_PARAMS = 34692
 
 
@@ -87,6 +88,8 @@ def lib():
         L.sphbi_pressure_contact.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, d, i64, vp, vp, vp, vp,
                                              i64, vp, vp, vp, i64, vp, vp, vp, vp, C.c_size_t, vp]
         f = C.c_float
+        L.sphbi_integrate_quadrature.argtypes = [C.POINTER(SphbiKernel), d, i32, i32, i64, vp, vp, i64, vp, vp,
+                                                 vp, vp, i64, vp, vp, vp, vp]
         L.sphbi_surrogate_features.argtypes = [d, i64, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
         L.sphbi_surrogate_targets.argtypes = [i64, d, vp, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp, vp]
         L.sphbi_mlp_workspace.argtypes = [i64]
@@ -357,6 +360,29 @@ def pressure_contact(kernel, h, rho0, px, py, p_particle, rho_particle, tri, off
                                         _ptr(tri_idx), P, _ptr(p_pair), _ptr(ax), _ptr(ay), _ptr(ws), ws.numel(),
                                         _stream()), "sphbi_pressure_contact")
     return ax, ay
+
+
+# ----------------------------------------------------------------------------
+# quadrature of the same sums (the comparison of Sec. 6.1-6.2)
+# ----------------------------------------------------------------------------
+MAX_GAUSS = 64
+
+
+def integrate_quadrature(kernel, h, px, py, tri, nodal, offsets, tri_idx, n_gauss):
+    """``sphbi_integrate_quadrature``: per-particle (I, Gx, Gy) [N] with an
+    n_gauss x n_gauss collapsed Gauss-Legendre rule per pair."""
+    k = kernel_preset(kernel) if isinstance(kernel, int) else kernel
+    px, py, tri, nodal = _dev(px), _dev(py), _dev(tri), _dev(nodal)
+    offsets, tri_idx = _dev(offsets, torch.int64), _dev(tri_idx, torch.int32)
+    N, T, P = px.numel(), tri.shape[1], tri_idx.numel()
+    if nodal.shape[-1] != T or offsets.numel() != N + 1:
+        raise SphbiError("nodal must be [n_nodes, T] and offsets [N + 1]")
+    I = torch.empty(N, dtype=torch.float64, device=px.device)
+    Gx, Gy = torch.empty_like(I), torch.empty_like(I)
+    _check(lib().sphbi_integrate_quadrature(C.byref(k), float(h), int(nodal.shape[0]), int(n_gauss), N, _ptr(px),
+                                            _ptr(py), T, _ptr(tri), _ptr(nodal), _ptr(offsets), _ptr(tri_idx), P,
+                                            _ptr(I), _ptr(Gx), _ptr(Gy), _stream()), "sphbi_integrate_quadrature")
+    return I, Gx, Gy
 
 
 # ----------------------------------------------------------------------------

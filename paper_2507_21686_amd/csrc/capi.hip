@@ -540,6 +540,29 @@ int sphbi_integrate(const sphbi_kernel *kernel, const sphbi_opts *opts, double h
                                     n_pairs, I, Gx, Gy, per_pair, stream);
 }
 
+int sphbi_integrate_quadrature(const sphbi_kernel *kernel, double h, int32_t n_nodes, int32_t n_gauss, int64_t N,
+                               const double *px, const double *py, int64_t T, const double *tri,
+                               const double *nodal, const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs,
+                               double *I, double *Gx, double *Gy, void *stream) {
+    sphbi_opts o;
+    int rc = check_common(kernel, nullptr, &o, h, n_nodes, N, T, n_pairs);
+    if (rc) return rc;
+    if (n_gauss < 1 || n_gauss > SPHBI_MAX_GAUSS) {
+        set_error("n_gauss must be in [1, %d]", SPHBI_MAX_GAUSS);
+        return SPHBI_EINVAL;
+    }
+    if (N > 0 && (!px || !py || !offsets || !I || !Gx || !Gy)) { set_error("particle arrays are NULL"); return SPHBI_EINVAL; }
+    if (n_pairs > 0 && (!tri_idx || !tri || !nodal)) { set_error("pair/triangle arrays are NULL"); return SPHBI_EINVAL; }
+    const void *ptrs[] = {px, py, tri, nodal, offsets, tri_idx, I, Gx, Gy};
+    for (const void *p : ptrs)
+        if (!aligned8(p)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
+    int deg = 0;
+    const KArgs K = make_kargs(kernel, &deg);
+    const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
+    return launch_quadrature(order, deg, n_gauss, K, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, I, Gx,
+                             Gy, (hipStream_t)stream);
+}
+
 size_t sphbi_integrate_backward_workspace(int64_t T, int64_t n_pairs, int32_t n_nodes) {
     return backward_workspace(T > 0 ? T : 0, n_pairs > 0 ? n_pairs : 0, n_nodes == 10 ? 10 : (n_nodes == 3 ? 3 : 1));
 }

@@ -10,6 +10,7 @@ namespace sphbi {
 
 constexpr int kMaxOrder = 3;    // cubic fields
 constexpr int kMaxDeg = 11;     // kernel polynomial degree
+constexpr int kMaxGauss = SPHBI_MAX_GAUSS;   // Gauss-Legendre points per direction (quadrature path)
 
 // Device-side kernel description, derived on the host from sphbi_kernel.
 // R[p], iR[p]  = piece radius and its inverse (units of h)
@@ -64,6 +65,11 @@ int launch_pressure_contact(int deg, const KArgs &K, double h, double rho0, int6
                             const double *py, const double *p_i, const double *rho_i, const int64_t *off,
                             const int32_t *tri_idx, int64_t P, int64_t T, const double *tri, const double *p_pair,
                             double *ax, double *ay, void *ws, hipStream_t s);
+// numerical quadrature of the same sums: n_gauss x n_gauss collapsed
+// Gauss-Legendre points per triangle (1 <= n_gauss <= kMaxGauss)
+int launch_quadrature(int order, int deg, int n_gauss, const KArgs &K, double h, int64_t N, const double *px,
+                      const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T,
+                      const double *tri, const double *nodal, double *I, double *Gx, double *Gy, hipStream_t s);
 // the adjoint pair kernel for linear fields (its own translation unit)
 void launch_adjoint_linear(int deg, const KArgs &K, double invh, int64_t N, const double *px, const double *py,
                            const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,

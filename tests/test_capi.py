@@ -134,3 +134,24 @@ def test_pressure_contact_arguments_rejected_without_device():
     assert call(opts=sb.opts(sb.MIXED)) == -2
     assert call(p_pair=z) == -1
     assert call(ws_bytes=need - 8) == -4
+
+
+def test_quadrature_arguments_rejected_without_device():
+    """sphbi_integrate_quadrature validates before any launch."""
+    L = sb.lib()
+    k = sb.kernel_preset(1)
+    z = C.c_void_p(None)
+    host = np.zeros(64, dtype=np.float64)            # stand-in pointers: never dereferenced on these paths
+    p = C.c_void_p(host.ctypes.data)
+
+    def call(n_gauss=8, h=1.0, n_nodes=3, N=4, px=p, tri=p):
+        return L.sphbi_integrate_quadrature(C.byref(k), h, n_nodes, n_gauss, N, px, p, 2, tri, p, p, p, 8, p, p, p,
+                                            z)
+
+    assert call(n_gauss=0) == -1 and b"n_gauss" in L.sphbi_last_error()
+    assert call(n_gauss=sb.MAX_GAUSS + 1) == -1
+    assert call(h=0.0) == -1
+    assert call(n_nodes=4) == -1
+    assert call(px=z) == -1
+    assert call(tri=z) == -1
+    assert call(N=0) == 0                              # nothing to do, nothing launched

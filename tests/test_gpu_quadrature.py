@@ -1,0 +1,177 @@
+"""GPU parity of the quadrature path (sphbi_integrate_quadrature; the
+comparison of Sec. 6.1-6.2) against the oracle's collapsed Gauss-Legendre
+quadrature (oracle/quadrature.py, pinned in test_oracle_quadrature.py).
+
+Both sides evaluate the same n x n points per pair.  They differ in the order
+of the sums and in how the kernel polynomial is evaluated (fused Horner on the
+GPU, numpy's polyval on the CPU); the latter dominates: the monomial form
+of k' cancels near the support radius, and its rounding is bounded by
+(deg + 1) eps sum_k k |b_k| per point, against a gradient scale of 2 int k
+(tests/metrics.py).  The tolerance is that bound with deg + 1 <= 16, doubled
+for cubic fields, whose basis adds its own rounding.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import quadrature as Q
+import paper_2507_21686_amd as sb
+from paper_2507_21686_amd import workloads as W
+from tests import exact, metrics
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+NTH = 16
+
+
+def quad_tol(kid, order=0):
+    """16 eps times the larger rounding amplification of k' (against the
+    gradient scale 2 int k) and of k (C_d sum |b_k| R^k over the support
+    disc's area pi, against the value scale 1)."""
+    n, R, deg, b, cd = oracle.kernel_monomials(kid)
+    k = [np.arange(deg[p] + 1) for p in range(n)]
+    cond_g = sum((k[p] * np.abs(b[p][:deg[p] + 1]) * R[p] ** np.maximum(k[p] - 1, 0)).sum()
+                 for p in range(n)) / float(2 * exact.int_k(kid))
+    cond_i = np.pi * cd * sum((np.abs(b[p][:deg[p] + 1]) * R[p] ** k[p]).sum() for p in range(n))
+    return 16 * 1.11e-16 * max(cond_g, cond_i) * (2.0 if order == 3 else 1.0)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV, dtype=dtype)
+
+
+def gpu_quad(wl, off, idx, n, px=None, py=None, nodal=None):
+    px = wl.px if px is None else px
+    py = wl.py if py is None else py
+    nodal = wl.nodal if nodal is None else nodal
+    out = sb.integrate_quadrature(wl.kernel, wl.h, dev(px), dev(py), dev(wl.tri), dev(nodal),
+                                  dev(off, torch.int64), dev(idx, torch.int32), n)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in out]
+
+
+def scaled(wl, got, ref, sel=None):
+    """max scale-normalised error of (I, Gx, Gy)"""
+    amax = np.abs(wl.nodal).max() * (3.0 if wl.n_nodes == 10 else 1.0)
+    sel = np.arange(len(got[0])) if sel is None else sel
+    sI, sG = amax, metrics.grad_scale(wl.kernel, wl.h) * amax
+    return max(float(metrics.scaled_err(got[0][sel], ref[0], sI).max(initial=0.0)),
+               float(metrics.scaled_err(got[1][sel], ref[1], sG).max(initial=0.0)),
+               float(metrics.scaled_err(got[2][sel], ref[2], sG).max(initial=0.0)))
+
+
+def sub_csr(off, idx, sel):
+    soff = np.concatenate([[0], np.cumsum(off[sel + 1] - off[sel])]).astype(np.int64)
+    sidx = np.concatenate([idx[off[i]:off[i + 1]] for i in sel]).astype(np.int32) if len(sel) else np.zeros(0, np.int32)
+    return soff, sidx
+
+
+@pytest.mark.parametrize("kid", [0, 1, 2, 3])
+@pytest.mark.parametrize("order", [0, 1, 3])
+@pytest.mark.parametrize("n", [1, 4, 9])
+def test_quadrature_parity_covering_small(kid, order, n):
+    wl = W.covering_workload(n_side=32, nx=4, ny=8, seed=3 + kid, kernel=kid, field_order=order)
+    say(f"quadrature covering kernel={kid} n_nodes={wl.n_nodes} n={n}")
+    off, idx = oracle.pairlist(wl.px, wl.py, wl.tri, wl.h, nthreads=NTH)
+    got = gpu_quad(wl, off, idx, n)
+    ref = Q.integrate(wl.kernel, wl.h, wl.px, wl.py, wl.tri, wl.nodal, off, idx, n)
+    err = scaled(wl, got, ref)
+    say(f"  pairs={off[-1]} err={err:.2e}")
+    assert err <= quad_tol(kid, order)
+
+
+@pytest.mark.parametrize("n", [3, 16])
+def test_quadrature_parity_band_wall(n):
+    wl = W.band_wall(seed=4, kernel=1, field_order=1)
+    off, idx = oracle.pairlist(wl.px, wl.py, wl.tri, wl.h, nthreads=NTH)
+    got = gpu_quad(wl, off, idx, n)
+    ref = Q.integrate(wl.kernel, wl.h, wl.px, wl.py, wl.tri, wl.nodal, off, idx, n)
+    err = scaled(wl, got, ref)
+    say(f"quadrature band wall n={n}: pairs={off[-1]} err={err:.2e}")
+    assert err <= quad_tol(1, 1)
+
+
+def test_quadrature_full_size_sampled():
+    """The 1,048,576-particle C2/P3 workload at n = 8, 1,024 sampled particles."""
+    wl = W.covering_workload(n_side=1024, nx=128, ny=256, seed=2)
+    t = [dev(a) for a in (wl.px, wl.py, wl.tri)]
+    off_t, idx_t = sb.pairlist(*t, wl.h)
+    off, idx = off_t.cpu().numpy(), idx_t.cpu().numpy()
+    got = gpu_quad(wl, off, idx, 8)
+    sel = np.sort(np.random.default_rng(9).choice(wl.n_particles, 1024, replace=False))
+    soff, sidx = sub_csr(off, idx, sel)
+    ref = Q.integrate(wl.kernel, wl.h, wl.px[sel], wl.py[sel], wl.tri, wl.nodal, soff, sidx, 8)
+    err = scaled(wl, got, ref, sel)
+    say(f"quadrature full size: pairs={off[-1]} err={err:.2e}")
+    assert err <= quad_tol(wl.kernel, 3)
+
+
+def test_quadrature_edge_cases():
+    wl = W.covering_workload(n_side=16, nx=3, ny=6, seed=5, kernel=0, field_order=1)
+    off, idx = oracle.pairlist(wl.px, wl.py, wl.tri, wl.h, nthreads=NTH)
+    T, N = wl.n_triangles, wl.n_particles
+    ref = gpu_quad(wl, off, idx, 5)
+    # out-of-range triangle indices contribute nothing
+    off2 = off + np.arange(N + 1)
+    idx2 = np.empty(len(idx) + N, np.int32)
+    for i in range(N):
+        idx2[off2[i]:off2[i + 1] - 1] = idx[off[i]:off[i + 1]]
+        idx2[off2[i + 1] - 1] = T + 3 if i % 2 else -1
+    got = gpu_quad(wl, off2, idx2, 5)
+    assert all(np.array_equal(g, r) for g, r in zip(got, ref))
+    # deterministic
+    again = gpu_quad(wl, off, idx, 5)
+    assert all(np.array_equal(g, r) for g, r in zip(again, ref))
+    # particles without pairs give zeros
+    got = gpu_quad(wl, np.zeros(N + 1, np.int64), np.zeros(0, np.int32), 5)
+    assert all(np.all(g == 0.0) for g in got)
+    # no particles: nothing to do
+    out = sb.integrate_quadrature(0, wl.h, dev(np.zeros(0)), dev(np.zeros(0)), dev(wl.tri), dev(wl.nodal),
+                                  dev(np.zeros(1), torch.int64), dev(np.zeros(0), torch.int32), 5)
+    assert all(o.numel() == 0 for o in out)
+    # the largest rule against the oracle
+    got = gpu_quad(wl, off, idx, sb.MAX_GAUSS)
+    ref64 = Q.integrate(wl.kernel, wl.h, wl.px, wl.py, wl.tri, wl.nodal, off, idx, sb.MAX_GAUSS)
+    assert scaled(wl, got, ref64) <= quad_tol(0, 1)
+    with pytest.raises(sb.SphbiError):
+        gpu_quad(wl, off, idx, sb.MAX_GAUSS + 1)
+
+
+@pytest.mark.parametrize("kid", [0, 1, 2, 3])
+def test_quadrature_e3_e4_on_gpu(kid):
+    """E3/E4 (Sec. 6.2): [-1,1]^2 in 8 triangles, x = 0, h = 1; f = 1 -> (1, 0, 0),
+    f = x -> (0, 1, 0).  The rule approaches them; the closed form meets them."""
+    tri = W.box_mesh_8()
+    T = tri.shape[1]
+    x = W.vertex_positions(tri)[:, 0]
+    z = dev(np.zeros(1))
+    off, idx = dev(np.array([0, T]), torch.int64), dev(np.arange(T), torch.int32)
+    e = []
+    for n in (8, 64):
+        I, gx, gy = [o.item() for o in sb.integrate_quadrature(kid, 1.0, z, z, dev(tri), dev(np.ones((1, T))), off,
+                                                                idx, n)]
+        I1, gx1, gy1 = [o.item() for o in sb.integrate_quadrature(kid, 1.0, z, z, dev(tri), dev(x), off, idx, n)]
+        e.append(max(abs(I - 1), abs(gx), abs(gy), abs(I1), abs(gx1 - 1), abs(gy1)))
+    cf = [o.item() for o in sb.integrate(kid, 1.0, z, z, dev(tri), dev(np.ones((1, T))), off, idx)]
+    say(f"E3/E4 kernel {kid}: quadrature n=8 {e[0]:.2e}, n=64 {e[1]:.2e}; closed form {abs(cf[0] - 1):.2e}")
+    assert e[1] < 1e-6 and e[1] < 1e-2 * e[0]
+    assert max(abs(cf[0] - 1), abs(cf[1]), abs(cf[2])) < 1e-12
+
+
+def test_quadrature_converges_to_closed_form():
+    """On a covering workload (C4, P1) the rule approaches the closed form as n
+    grows.  Its triangles are several h across, the large-triangle case of
+    Sec. 6.2: few points fall inside the support, so the approach is slow."""
+    wl = W.covering_workload(n_side=64, nx=8, ny=16, seed=6, kernel=1, field_order=1)
+    t = [dev(a) for a in (wl.px, wl.py, wl.tri, wl.nodal)]
+    off_t, idx_t = sb.pairlist(*t[:3], wl.h)
+    cf = [o.cpu().numpy() for o in sb.integrate(wl.kernel, wl.h, *t, off_t, idx_t)]
+    off, idx = off_t.cpu().numpy(), idx_t.cpu().numpy()
+    errs = [scaled(wl, gpu_quad(wl, off, idx, n), cf) for n in (4, 16, 48)]
+    say(f"quadrature vs closed form (C4, P1): n=4 {errs[0]:.2e}, n=16 {errs[1]:.2e}, n=48 {errs[2]:.2e}")
+    assert errs[1] < 0.1 * errs[0] and errs[2] < 0.1 * errs[1]
