@@ -13,8 +13,8 @@
 // exact for fields times polynomials of total degree <= 2n - 2 in (L1, L2).
 //
 // The Gauss-Legendre nodes are computed on the host by Newton's iteration on
-// the three-term Legendre recurrence and handed to the kernel by value.  One
-// thread per particle sums its pairs in pair order (deterministic).  FP64.
+// the three-term Legendre recurrence and handed to the kernel by value.  Sums
+// are taken in a fixed order (deterministic).  FP64.
 
 #include <math.h>
 
@@ -81,44 +81,58 @@ __device__ inline double field_at(const double *A, double L0, double L1, double 
     }
 }
 
+// Thread layout: every particle gets n threads; thread a of a particle takes
+// the outer Gauss row a (n points) of each of its pairs, in pair order, and
+// the n row sums are added in row order through LDS.  A block of 256 threads
+// holds ppb = floor(256 / n) particles.  n threads per particle keep the chip
+// busy when there are few particles; the sums stay deterministic, and a pair
+// with an invalid index changes nothing.
 template <int NN>
 __global__ __launch_bounds__(256) void quadrature_kernel(const QuadKernel K, const QuadRule Q, int deg, double h,
-                                                         int64_t N, const double *__restrict__ px,
+                                                         int ppb, int64_t N, const double *__restrict__ px,
                                                          const double *__restrict__ py,
                                                          const int64_t *__restrict__ off,
                                                          const int32_t *__restrict__ tri_idx, int64_t P, int64_t T,
                                                          const double *__restrict__ tri,
                                                          const double *__restrict__ nodal, double *__restrict__ I,
                                                          double *__restrict__ Gx, double *__restrict__ Gy) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const double x = px[i], y = py[i], invh = 1.0 / h;
-    const double sv = K.cd * invh * invh, sg = sv * invh;
-    int64_t lo = off[i], hi = off[i + 1];
-    lo = lo < 0 ? 0 : (lo > P ? P : lo);
-    hi = hi < lo ? lo : (hi > P ? P : hi);
+    __shared__ double s_x[kMaxGauss], s_w[kMaxGauss];
+    __shared__ double s_red[3][256];
+    const int n = Q.n;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        s_x[k] = Q.x[k];
+        s_w[k] = Q.w[k];
+    }
+    __syncthreads();
+    const int slot = threadIdx.x / n, a = threadIdx.x - slot * n;
+    const int64_t i = (int64_t)blockIdx.x * ppb + slot;
+    const bool act = slot < ppb && i < N;
+    const double invh = 1.0 / h;
     double si = 0.0, sx = 0.0, sy = 0.0;
-    for (int64_t q = lo; q < hi; ++q) {
-        const int32_t t = tri_idx[q];
-        if (t < 0 || t >= T) continue;
-        const double ax = tri[t], ay = tri[T + t], bx = tri[2 * T + t], by = tri[3 * T + t];
-        const double cx = tri[4 * T + t], cy = tri[5 * T + t];
-        double A[NN];
+    if (act) {
+        const double x = px[i], y = py[i];
+        int64_t lo = off[i], hi = off[i + 1];
+        lo = lo < 0 ? 0 : (lo > P ? P : lo);
+        hi = hi < lo ? lo : (hi > P ? P : hi);
+        const double u = s_x[a], wu = s_w[a] * (1.0 - u);
+        for (int64_t q = lo; q < hi; ++q) {
+            const int32_t t = tri_idx[q];
+            if (t < 0 || t >= T) continue;
+            const double ax = tri[t], ay = tri[T + t], bx = tri[2 * T + t], by = tri[3 * T + t];
+            const double cx = tri[4 * T + t], cy = tri[5 * T + t];
+            double A[NN];
 #pragma unroll
-        for (int k = 0; k < NN; ++k) A[k] = nodal[k * T + t];
-        const double area2 = fabs((bx - ax) * (cy - ay) - (by - ay) * (cx - ax));
-        double pi = 0.0, pxs = 0.0, pys = 0.0;
-        for (int a = 0; a < Q.n; ++a) {
-            const double u = Q.x[a], wu = Q.w[a] * (1.0 - u);
+            for (int k = 0; k < NN; ++k) A[k] = nodal[k * T + t];
+            const double area2 = fabs((bx - ax) * (cy - ay) - (by - ay) * (cx - ax));
             double ri = 0.0, rx = 0.0, ry = 0.0;
-            for (int b = 0; b < Q.n; ++b) {
-                const double L1 = u, L2 = (1.0 - u) * Q.x[b], L0 = 1.0 - L1 - L2;
+            for (int b = 0; b < n; ++b) {
+                const double L1 = u, L2 = (1.0 - u) * s_x[b], L0 = 1.0 - L1 - L2;
                 const double dx = (x - (L0 * ax + L1 * bx + L2 * cx)) * invh;
                 const double dy = (y - (L0 * ay + L1 * by + L2 * cy)) * invh;
                 const double r = sqrt(dx * dx + dy * dy);
                 double k, dk;
                 kernel_and_slope(K, deg, r, k, dk);
-                const double fw = field_at<NN>(A, L0, L1, L2) * Q.w[b];
+                const double fw = field_at<NN>(A, L0, L1, L2) * s_w[b];
                 ri += fw * k;
                 if (r > 0.0) {
                     const double g = fw * dk / r;
@@ -126,17 +140,28 @@ __global__ __launch_bounds__(256) void quadrature_kernel(const QuadKernel K, con
                     ry += g * dy;
                 }
             }
-            pi += wu * ri;
-            pxs += wu * rx;
-            pys += wu * ry;
+            const double c = area2 * wu;
+            si += c * ri;
+            sx += c * rx;
+            sy += c * ry;
         }
-        si += area2 * pi;
-        sx += area2 * pxs;
-        sy += area2 * pys;
     }
-    I[i] = sv * si;
-    Gx[i] = sg * sx;
-    Gy[i] = sg * sy;
+    s_red[0][threadIdx.x] = si;
+    s_red[1][threadIdx.x] = sx;
+    s_red[2][threadIdx.x] = sy;
+    __syncthreads();
+    if (act && a == 0) {
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+        for (int k = 0; k < n; ++k) {             // rows in order; threadIdx.x + k < ppb * n <= 256
+            t0 += s_red[0][threadIdx.x + k];
+            t1 += s_red[1][threadIdx.x + k];
+            t2 += s_red[2][threadIdx.x + k];
+        }
+        const double sv = K.cd * invh * invh, sg = sv * invh;
+        I[i] = sv * t0;
+        Gx[i] = sg * t1;
+        Gy[i] = sg * t2;
+    }
 }
 
 // Gauss-Legendre nodes and weights on [-1, 1]: Newton's iteration on P_n,
@@ -186,15 +211,16 @@ int launch_quadrature(int order, int deg, int n_gauss, const KArgs &K, double h,
     QuadRule Q{};
     Q.n = n_gauss;
     gauss_legendre01(n_gauss, Q.x, Q.w);
-    const unsigned nb = (unsigned)((N + 255) / 256);
+    const int ppb = 256 / n_gauss;
+    const unsigned nb = (unsigned)((N + ppb - 1) / ppb);
     if (order == 0)
-        hipLaunchKernelGGL(quadrature_kernel<1>, dim3(nb), dim3(256), 0, s, QK, Q, deg, h, N, px, py, off, tri_idx, P,
+        hipLaunchKernelGGL(quadrature_kernel<1>, dim3(nb), dim3(256), 0, s, QK, Q, deg, h, ppb, N, px, py, off, tri_idx, P,
                            T, tri, nodal, I, Gx, Gy);
     else if (order == 1)
-        hipLaunchKernelGGL(quadrature_kernel<3>, dim3(nb), dim3(256), 0, s, QK, Q, deg, h, N, px, py, off, tri_idx, P,
+        hipLaunchKernelGGL(quadrature_kernel<3>, dim3(nb), dim3(256), 0, s, QK, Q, deg, h, ppb, N, px, py, off, tri_idx, P,
                            T, tri, nodal, I, Gx, Gy);
     else
-        hipLaunchKernelGGL(quadrature_kernel<10>, dim3(nb), dim3(256), 0, s, QK, Q, deg, h, N, px, py, off, tri_idx, P,
+        hipLaunchKernelGGL(quadrature_kernel<10>, dim3(nb), dim3(256), 0, s, QK, Q, deg, h, ppb, N, px, py, off, tri_idx, P,
                            T, tri, nodal, I, Gx, Gy);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("quadrature launch: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
