@@ -155,3 +155,21 @@ def test_quadrature_arguments_rejected_without_device():
     assert call(px=z) == -1
     assert call(tri=z) == -1
     assert call(N=0) == 0                              # nothing to do, nothing launched
+
+
+def test_binding_fails_loudly_without_library_or_device(monkeypatch):
+    """No CPU fallback: a missing library raises, and so do host tensors."""
+    import torch
+    monkeypatch.setattr(sb, "_lib", None)
+    monkeypatch.setattr(sb, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libsphbi.so"))
+    with pytest.raises(sb.SphbiError, match="missing"):
+        sb.lib()
+    monkeypatch.undo()
+    x = torch.zeros(4, dtype=torch.float64)
+    tri = torch.zeros(6, 2, dtype=torch.float64)
+    with pytest.raises(sb.SphbiError, match="GPU"):
+        sb.integrate_quadrature(0, 1.0, x, x, tri, torch.zeros(1, 2, dtype=torch.float64),
+                                torch.zeros(5, dtype=torch.int64), torch.zeros(0, dtype=torch.int32), 4)
+    with pytest.raises(sb.SphbiError, match="GPU"):
+        sb.integrate(0, 1.0, x, x, tri, torch.zeros(1, 2, dtype=torch.float64), torch.zeros(5, dtype=torch.int64),
+                     torch.zeros(0, dtype=torch.int32))
