@@ -212,6 +212,10 @@ int launch_quadrature(int order, int deg, int n_gauss, const KArgs &K, double h,
     Q.n = n_gauss;
     gauss_legendre01(n_gauss, Q.x, Q.w);
     const int ppb = 256 / n_gauss;
+    if ((N + ppb - 1) / ppb > (int64_t)INT32_MAX) {
+        set_error("too many particles for one quadrature launch (%lld)", (long long)N);
+        return SPHBI_EUNSUPPORTED;
+    }
     const unsigned nb = (unsigned)((N + ppb - 1) / ppb);
     if (order == 0)
         hipLaunchKernelGGL(quadrature_kernel<1>, dim3(nb), dim3(256), 0, s, QK, Q, deg, h, ppb, N, px, py, off, tri_idx, P,
