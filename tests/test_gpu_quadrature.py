@@ -37,6 +37,9 @@ def quad_tol(kid, order=0):
     return 16 * 1.11e-16 * max(cond_g, cond_i) * (2.0 if order == 3 else 1.0)
 
 
+CLOSED_FORM_TOL = {0: 2e-13, 1: 5e-13, 2: 4e-12, 3: 2e-13}     # the forward parity tolerances
+
+
 def say(msg):
     print(msg, flush=True)
 
@@ -175,3 +178,26 @@ def test_quadrature_converges_to_closed_form():
     errs = [scaled(wl, gpu_quad(wl, off, idx, n), cf) for n in (4, 16, 48)]
     say(f"quadrature vs closed form (C4, P1): n=4 {errs[0]:.2e}, n=16 {errs[1]:.2e}, n=48 {errs[2]:.2e}")
     assert errs[1] < 0.1 * errs[0] and errs[2] < 0.1 * errs[1]
+
+
+@pytest.mark.parametrize("kid", [0, 1, 2, 3])
+@pytest.mark.parametrize("n_nodes", [1, 3, 10])
+def test_quadrature_meets_closed_form_on_smooth_integrand(kid, n_nodes):
+    """Two independent device paths agree where the integrand is smooth: a
+    triangle inside one annulus of the support, away from the particle and
+    from every piece radius, where the rule converges exponentially."""
+    h = 0.7
+    tri = np.array([[0.6, 0.1, 0.85, 0.2, 0.7, 0.4]]).T * h + np.array([[0.3, -0.2] * 3]).T
+    A = np.random.default_rng(kid + 7 * n_nodes).standard_normal((n_nodes, 1))
+    px, py = dev(np.array([0.3])), dev(np.array([-0.2]))
+    off, idx = dev(np.array([0, 1]), torch.int64), dev(np.array([0]), torch.int32)
+    cf = np.array([o.item() for o in sb.integrate(kid, h, px, py, dev(tri), dev(A), off, idx)])
+    q = np.array([o.item() for o in sb.integrate_quadrature(kid, h, px, py, dev(tri), dev(A), off, idx, 14)])
+    amax = np.abs(A).max() * (3.0 if n_nodes == 10 else 1.0)
+    scale = np.array([amax, metrics.grad_scale(kid, h) * amax, metrics.grad_scale(kid, h) * amax])
+    err = float((np.abs(q - cf) / np.maximum(np.abs(cf), scale)).max())
+    order = {1: 0, 3: 1, 10: 3}[n_nodes]
+    # each path within its own bound: the closed form's forward tolerance, the rule's rounding bound
+    bound = CLOSED_FORM_TOL[kid] * (10.0 if order == 3 else 1.0) + quad_tol(kid, order)
+    say(f"smooth annulus kernel={kid} n_nodes={n_nodes}: quadrature n=14 vs closed form {err:.2e} (bound {bound:.1e})")
+    assert err <= bound
