@@ -148,6 +148,27 @@ int sphbi_integrate(const sphbi_kernel *kernel /* host */, const sphbi_opts *opt
                     size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------
+ * sphbi_integrate without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation).  Same arguments, results and status codes as
+ * sphbi_integrate, minus ws/ws_bytes.  The per-triangle field records go to
+ * a fixed array inside this library (one copy per GPU, allocated with the
+ * code object and held until the process ends) of SPHBI_NOALLOC_MAX_TRIANGLES
+ * records, 16 MiB; T above that returns SPHBI_EUNSUPPORTED and launches
+ * nothing.  No call allocates or frees memory.  The first call on a device
+ * looks up that device's array address (synchronous, once per device).
+ * Every call on one GPU shares its array: calls that overlap in time on
+ * the same GPU (different streams or threads) race and must be ordered by
+ * the caller.  Asynchronous.
+ * ------------------------------------------------------------------- */
+#define SPHBI_NOALLOC_MAX_TRIANGLES 131072
+
+int sphbi_integrate_noalloc(const sphbi_kernel *kernel /* host */, const sphbi_opts *opts /* host, NULL = default */,
+                            double h, int32_t n_nodes, int64_t N, const double *px, const double *py, int64_t T,
+                            const double *tri, const double *nodal, const int64_t *offsets, const int32_t *tri_idx,
+                            int64_t n_pairs, double *I, double *Gx, double *Gy, double *per_pair, void *stream);
+
+/* ---------------------------------------------------------------------
  * The two stages of sphbi_integrate, for callers that reuse the per-triangle
  * field records across calls (static boundary, repeated evaluation) or time
  * the pair kernel alone.

@@ -27,8 +27,9 @@ EXPORTS = ["sphbi_kernel_preset", "sphbi_default_opts", "sphbi_last_error", "sph
            "sphbi_integrate_backward", "sphbi_surrogate_features", "sphbi_surrogate_targets", "sphbi_mlp_workspace", "sphbi_mlp_forward",
            "sphbi_mlp_loss_grad", "sphbi_adam_step", "sphbi_surrogate_model_bytes", "sphbi_surrogate_pack",
            "sphbi_surrogate_workspace", "sphbi_surrogate_integrate", "sphbi_operator_workspace", "sphbi_operator",
-           "sphbi_pressure_contact", "sphbi_integrate_quadrature"]
+           "sphbi_pressure_contact", "sphbi_integrate_quadrature", "sphbi_integrate_noalloc"]
 MLP_PARAMS = 34692
+NOALLOC_MAX_TRIANGLES = 131072
 
 
 class SphbiKernel(C.Structure):
@@ -73,6 +74,8 @@ def lib():
         L.sphbi_integrate_workspace.restype = C.c_size_t
         L.sphbi_integrate.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, i32, i64, vp, vp, i64, vp,
                                       vp, vp, vp, i64, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.sphbi_integrate_noalloc.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, i32, i64, vp, vp,
+                                              i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp]
         L.sphbi_field_prepare.argtypes = [d, i32, i64, vp, vp, vp, C.c_size_t, vp]
         L.sphbi_integrate_prepared.argtypes = [C.POINTER(SphbiKernel), C.POINTER(SphbiOpts), d, i32, i64, vp, vp,
                                                i64, vp, vp, vp, i64, vp, vp, vp, vp, vp]
@@ -226,6 +229,33 @@ class Integrator:
                                      _ptr(Gx), _ptr(Gy), _ptr(pp), _ptr(ws), ws.numel(), _stream()),
                "sphbi_integrate")
         return (I, Gx, Gy, pp) if per_pair else (I, Gx, Gy)
+
+
+def integrate_noalloc(kernel, h, px, py, tri, nodal, offsets, tri_idx, out, per_pair=None, precision=FP64,
+                      tau_edge=1e-4):
+    """``sphbi_integrate_noalloc``: :func:`integrate` into caller-provided outputs.
+
+    ``out`` = (I, Gx, Gy) float64 [N] device tensors; ``per_pair`` an optional
+    [3, P] tensor.  The library allocates nothing (its records live in a fixed
+    per-GPU array of NOALLOC_MAX_TRIANGLES triangles); this wrapper allocates
+    nothing either.
+    """
+    k = kernel_preset(kernel) if isinstance(kernel, int) else kernel
+    px, py, tri, nodal = _dev(px), _dev(py), _dev(tri), _dev(nodal)
+    offsets, tri_idx = _dev(offsets, torch.int64), _dev(tri_idx, torch.int32)
+    I, Gx, Gy = (_dev(t) for t in out)
+    N, T, P, nn = px.numel(), tri.shape[1], tri_idx.numel(), nodal.shape[0]
+    if nodal.shape[1] != T:
+        raise SphbiError("nodal must be [n_nodes, T]")
+    if I.numel() != N or Gx.numel() != N or Gy.numel() != N:
+        raise SphbiError("outputs must be [N]")
+    if per_pair is not None and (_dev(per_pair).shape != (3, P)):
+        raise SphbiError("per_pair must be [3, P]")
+    o = opts(precision, tau_edge)
+    _check(lib().sphbi_integrate_noalloc(C.byref(k), C.byref(o), float(h), nn, N, _ptr(px), _ptr(py), T, _ptr(tri),
+                                         _ptr(nodal), _ptr(offsets), _ptr(tri_idx), P, _ptr(I), _ptr(Gx), _ptr(Gy),
+                                         _ptr(per_pair), _stream()), "sphbi_integrate_noalloc")
+    return I, Gx, Gy
 
 
 def integrate_backward(kernel, h, px, py, tri, nodal, offsets, tri_idx, gI, gGx, gGy):

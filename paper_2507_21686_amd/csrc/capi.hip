@@ -517,18 +517,37 @@ int sphbi_integrate_prepared(const sphbi_kernel *kernel, const sphbi_opts *opts,
                           Gx, Gy, per_pair, (hipStream_t)stream);
 }
 
-int sphbi_integrate(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,
-                    const double *px, const double *py, int64_t T, const double *tri, const double *nodal,
-                    const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, double *I, double *Gx,
-                    double *Gy, double *per_pair, void *ws, size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+namespace sphbi {
+
+int check_integrate_args(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,
+                         const double *px, const double *py, int64_t T, const double *tri, const double *nodal,
+                         const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, const double *I,
+                         const double *Gx, const double *Gy, const double *per_pair) {
     sphbi_opts o;
     int rc = check_common(kernel, opts, &o, h, n_nodes, N, T, n_pairs);
     if (rc) return rc;
     if (N > 0 && (!px || !py || !offsets || !I || !Gx || !Gy)) { set_error("particle arrays are NULL"); return SPHBI_EINVAL; }
     if (n_pairs > 0 && (!tri_idx || !tri || !nodal)) { set_error("pair/triangle arrays are NULL"); return SPHBI_EINVAL; }
-    const void *ptrs[] = {px, py, tri, nodal, offsets, tri_idx, I, Gx, Gy, per_pair, ws};
+    const void *ptrs[] = {px, py, tri, nodal, offsets, tri_idx, I, Gx, Gy, per_pair};
     for (const void *p : ptrs)
         if (!aligned8(p)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
+    return SPHBI_OK;
+}
+
+}  // namespace sphbi
+
+extern "C" {
+
+int sphbi_integrate(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,
+                    const double *px, const double *py, int64_t T, const double *tri, const double *nodal,
+                    const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, double *I, double *Gx,
+                    double *Gy, double *per_pair, void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_integrate_args(kernel, opts, h, n_nodes, N, px, py, T, tri, nodal, offsets, tri_idx, n_pairs, I,
+                                  Gx, Gy, per_pair);
+    if (rc) return rc;
+    if (!aligned8(ws)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
     if (N == 0) return SPHBI_OK;
     if (T > 0 && (!ws || ws_bytes < sphbi_integrate_workspace(T))) {
         set_error("workspace too small (%zu < %zu)", ws_bytes, sphbi_integrate_workspace(T));
@@ -536,7 +555,7 @@ int sphbi_integrate(const sphbi_kernel *kernel, const sphbi_opts *opts, double h
     }
     rc = sphbi_field_prepare(h, n_nodes, T, tri, nodal, (double *)ws, ws_bytes, stream);
     if (rc) return rc;
-    return sphbi_integrate_prepared(kernel, &o, h, n_nodes, N, px, py, T, (const double *)ws, offsets, tri_idx,
+    return sphbi_integrate_prepared(kernel, opts, h, n_nodes, N, px, py, T, (const double *)ws, offsets, tri_idx,
                                     n_pairs, I, Gx, Gy, per_pair, stream);
 }
 

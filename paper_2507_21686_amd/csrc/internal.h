@@ -39,6 +39,11 @@ struct KArgs {
 constexpr int kRecDoubles = 16;
 
 void set_error(const char *fmt, ...);
+// argument checks of sphbi_integrate (everything but the workspace)
+int check_integrate_args(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,
+                         const double *px, const double *py, int64_t T, const double *tri, const double *nodal,
+                         const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, const double *I,
+                         const double *Gx, const double *Gy, const double *per_pair);
 KArgs make_kargs(const sphbi_kernel *k, int *deg_out);
 
 int launch_prepare(int order, int64_t T, const double *tri, const double *nodal, double h, double *rec,
