@@ -34,6 +34,14 @@
  *    1/3, 2/3; edge v2->v0 at 1/3, 2/3; centroid.
  *  - Zero-area triangles contribute 0.  Either vertex orientation gives the
  *    same result.  Overlapping triangles are summed, not checked (Sec. 2).
+ *  - Pairs of tri_idx outside [offsets[0], offsets[N]) belong to no particle:
+ *    they contribute nothing to any output (their per_pair slots are left
+ *    as they were).  Offsets must be non-decreasing; offsets outside [0, P]
+ *    are clamped, so a malformed list never makes a kernel read out of
+ *    bounds.
+ *  - One call handles at most 2^28 - 256 particles and as many triangles
+ *    (every launch's grid must fit a 32-bit thread count); larger sizes
+ *    return SPHBI_EUNSUPPORTED before any launch.
  *  - Return value: SPHBI_OK or a negative status; sphbi_last_error() gives a
  *    message (thread-local).
  */

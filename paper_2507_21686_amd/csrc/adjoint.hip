@@ -62,14 +62,21 @@ __global__ __launch_bounds__(256) void tri_reduce(int64_t T, int n_nodes, const 
     else if (k < 6 + n_nodes) dnodal[(k - 6) * T + t] = acc;
 }
 
-// Sort keys: the triangle index, or T for an index outside [0, T) (such pairs
-// contribute nothing and sort after every triangle's run).
-__global__ void sort_keys(int64_t P, int64_t T, const int32_t *__restrict__ tri_idx, uint32_t *__restrict__ key,
+// Sort keys: the triangle index, or T for a pair that contributes nothing:
+// an index outside [0, T), or a pair outside the particles' range
+// [offsets[0], offsets[N]) of the CSR list, which the pair kernel does not
+// visit (and whose gradient slots it leaves unwritten).  Such pairs sort
+// after every triangle's run.
+__global__ void sort_keys(int64_t P, int64_t T, int64_t N, const int64_t *__restrict__ off,
+                          const int32_t *__restrict__ tri_idx, uint32_t *__restrict__ key,
                           int32_t *__restrict__ iota) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
+    // the pair kernel's own clamping of the range
+    const int64_t hi = N > 0 ? min(max(off[N], (int64_t)0), P) : 0;
+    const int64_t lo = N > 0 ? min(max(off[0], (int64_t)0), hi) : 0;
     const int32_t t = tri_idx[i];
-    key[i] = (t >= 0 && t < T) ? (uint32_t)t : (uint32_t)T;
+    key[i] = (i >= lo && i < hi && t >= 0 && t < T) ? (uint32_t)t : (uint32_t)T;
     iota[i] = (int32_t)i;
 }
 
@@ -127,7 +134,8 @@ int launch_backward(int order, int deg, const KArgs &K, double h, int64_t N, con
     if (e != hipSuccess) { set_error("adjoint launch: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
     if (T == 0) return SPHBI_OK;
     if (P > 0) {
-        hipLaunchKernelGGL(sort_keys, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, P, T, tri_idx, keys_in, iota);
+        hipLaunchKernelGGL(sort_keys, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, P, T, N, off, tri_idx, keys_in,
+                           iota);
         int bits = 1;                                  // keys are in [0, T]
         while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)T) ++bits;
         e = hipcub::DeviceRadixSort::SortPairs(w, tmp, keys_in, keys, iota, perm, (int)P, 0, bits, s);

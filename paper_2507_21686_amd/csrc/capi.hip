@@ -321,7 +321,10 @@ static int check_pairlist_args(int64_t N, const double *px, const double *py, in
     if (N > 0 && (!px || !py)) { set_error("particle arrays are NULL"); return SPHBI_EINVAL; }
     if (T > 0 && !tri) { set_error("triangle array is NULL"); return SPHBI_EINVAL; }
     if (!aligned8(px) || !aligned8(py) || !aligned8(tri)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
-    if (T > INT32_MAX) { set_error("more than 2^31-1 triangles"); return SPHBI_EUNSUPPORTED; }
+    if (N > kMaxItems || T > kMaxItems) {
+        set_error("more than %lld particles or triangles in one call", (long long)kMaxItems);
+        return SPHBI_EUNSUPPORTED;
+    }
     return SPHBI_OK;
 }
 
@@ -476,7 +479,10 @@ static int check_common(const sphbi_kernel *kernel, const sphbi_opts *opts, sphb
     if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
     if (n_nodes != 1 && n_nodes != 3 && n_nodes != 10) { set_error("n_nodes must be 1, 3 or 10"); return SPHBI_EINVAL; }
     if (N < 0 || T < 0 || n_pairs < 0) { set_error("negative size"); return SPHBI_EINVAL; }
-    if (T > INT32_MAX) { set_error("more than 2^31-1 triangles"); return SPHBI_EUNSUPPORTED; }
+    if (N > kMaxItems || T > kMaxItems) {
+        set_error("more than %lld particles or triangles in one call", (long long)kMaxItems);
+        return SPHBI_EUNSUPPORTED;
+    }
     return SPHBI_OK;
 }
 
@@ -485,7 +491,7 @@ int sphbi_field_prepare(double h, int32_t n_nodes, int64_t T, const double *tri,
     if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
     if (n_nodes != 1 && n_nodes != 3 && n_nodes != 10) { set_error("n_nodes must be 1, 3 or 10"); return SPHBI_EINVAL; }
     if (T < 0) { set_error("negative size"); return SPHBI_EINVAL; }
-    if (T > INT32_MAX) { set_error("more than 2^31-1 triangles"); return SPHBI_EUNSUPPORTED; }
+    if (T > kMaxItems) { set_error("more than %lld triangles in one call", (long long)kMaxItems); return SPHBI_EUNSUPPORTED; }
     if (T == 0) return SPHBI_OK;
     if (!tri || !nodal || !rec) { set_error("triangle/nodal/record arrays are NULL"); return SPHBI_EINVAL; }
     if (!aligned8(tri) || !aligned8(nodal) || !aligned8(rec)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
@@ -684,6 +690,7 @@ int sphbi_surrogate_features(double h, int64_t N, const double *px, const double
                              float *rot, void *stream) {
     if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
     if (N < 0 || T < 0 || n_pairs < 0) { set_error("negative size"); return SPHBI_EINVAL; }
+    if (N > kMaxItems || n_pairs > INT32_MAX) { set_error("too many particles or pairs in one call"); return SPHBI_EUNSUPPORTED; }
     if (N > 0 && (!px || !py || !offsets)) { set_error("particle arrays are NULL"); return SPHBI_EINVAL; }
     if (n_pairs > 0 && (!tri_idx || !feats || !rot || (T > 0 && !tri))) { set_error("pair arrays are NULL"); return SPHBI_EINVAL; }
     const void *p8[] = {px, py, tri, offsets};
@@ -696,6 +703,7 @@ int sphbi_surrogate_features(double h, int64_t N, const double *px, const double
 int sphbi_surrogate_targets(int64_t n_pairs, double h, const double *per_pair, const float *rot, const float *mean,
                             const float *stdev, float *targets, void *stream) {
     if (n_pairs < 0 || !(h > 0.0) || !isfinite(h)) { set_error("invalid size or h"); return SPHBI_EINVAL; }
+    if (n_pairs > INT32_MAX) { set_error("more than 2^31-1 pairs in one call"); return SPHBI_EUNSUPPORTED; }
     if (!mean || !stdev) { set_error("NULL statistics"); return SPHBI_EINVAL; }
     if (n_pairs > 0 && (!per_pair || !rot || !targets)) { set_error("NULL array"); return SPHBI_EINVAL; }
     if (!aligned8(per_pair) || !aligned(rot, 4) || !aligned(targets, 4)) { set_error("misaligned array"); return SPHBI_EINVAL; }
@@ -781,7 +789,10 @@ int sphbi_surrogate_integrate(const sphbi_kernel *kernel, double h, int64_t N, c
     if (rc) return rc;
     if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
     if (N < 0 || T < 0 || n_pairs < 0) { set_error("negative size"); return SPHBI_EINVAL; }
-    if (T > INT32_MAX || n_pairs > INT32_MAX) { set_error("more than 2^31-1 triangles or pairs"); return SPHBI_EUNSUPPORTED; }
+    if (N > kMaxItems || T > kMaxItems || n_pairs > INT32_MAX) {
+        set_error("too many particles, triangles or pairs in one call");
+        return SPHBI_EUNSUPPORTED;
+    }
     if (N > 0 && (!px || !py || !offsets || !I || !Gx || !Gy || !n_flagged || !model)) { set_error("NULL array"); return SPHBI_EINVAL; }
     if (n_pairs > 0 && (!tri_idx || !flags || !tri || !nodal)) { set_error("pair/triangle arrays are NULL"); return SPHBI_EINVAL; }
     const void *p8[] = {px, py, tri, nodal, offsets, I, Gx, Gy, per_pair, n_flagged};

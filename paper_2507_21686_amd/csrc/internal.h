@@ -39,6 +39,15 @@ struct KArgs {
 constexpr int kRecDoubles = 16;
 
 void set_error(const char *fmt, ...);
+
+// A dispatch's grid size in threads is a 32-bit quantity: blocks * threads
+// must stay below 2^32.
+inline bool grid_fits(int64_t blocks, int threads) {
+    return blocks >= 0 && (uint64_t)blocks * (uint64_t)threads < ((uint64_t)1 << 32);
+}
+// Largest particle and triangle counts of one call: every launch sized by N
+// or T uses at most 16 threads per item (plus one block of slack).
+constexpr int64_t kMaxItems = ((int64_t)1 << 28) - 256;
 // argument checks of sphbi_integrate (everything but the workspace)
 int check_integrate_args(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,
                          const double *px, const double *py, int64_t T, const double *tri, const double *nodal,

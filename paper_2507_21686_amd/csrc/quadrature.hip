@@ -212,8 +212,9 @@ int launch_quadrature(int order, int deg, int n_gauss, const KArgs &K, double h,
     Q.n = n_gauss;
     gauss_legendre01(n_gauss, Q.x, Q.w);
     const int ppb = 256 / n_gauss;
-    if ((N + ppb - 1) / ppb > (int64_t)INT32_MAX) {
-        set_error("too many particles for one quadrature launch (%lld)", (long long)N);
+    if (!grid_fits((N + ppb - 1) / ppb, 256)) {
+        set_error("too many particles for one quadrature launch (%lld; at most %lld at n_gauss = %d)", (long long)N,
+                  (long long)((((int64_t)1 << 32) / 256 - 1) * ppb), n_gauss);
         return SPHBI_EUNSUPPORTED;
     }
     const unsigned nb = (unsigned)((N + ppb - 1) / ppb);

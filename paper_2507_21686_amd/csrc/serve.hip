@@ -397,6 +397,16 @@ __global__ void iota64_kernel(int64_t n, int64_t *__restrict__ out) {
     if (i < n) out[i] = i;
 }
 
+// Clears the routing flags (the serving kernel writes only the pairs of the
+// particles' CSR range [offsets[0], offsets[N]); the rest must read as "not
+// flagged") and the flagged count.  A kernel rather than a memset, so that a
+// captured graph replays it like any other node.
+__global__ void clear_flags_kernel(int64_t n, uint8_t *__restrict__ flags, int64_t *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flags[i] = 0;
+    if (i == 0 && count) *count = 0;
+}
+
 inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct ServeWs {
@@ -480,14 +490,13 @@ int surrogate_integrate(const KArgs &K, int deg, double h, int64_t N, const doub
     const int64_t n_waves = (N + 63) / 64;
     const int64_t want = (n_waves + kServeThreads / 64 - 1) / (kServeThreads / 64);
     const unsigned grid = (unsigned)(want < (int64_t)n_cu * 2 ? want : (int64_t)n_cu * 2);
+    hipLaunchKernelGGL(clear_flags_kernel, dim3((unsigned)((P + 255) / 256 > 0 ? (P + 255) / 256 : 1)), dim3(256), 0,
+                       s, P, flags, n_flagged);
     hipLaunchKernelGGL(serve_kernel, dim3(grid), dim3(kServeThreads), 0, s, (const Model *)model, invh, threshold, N,
                        px, py, T, tri, nodal, off, tri_idx, P, I, Gx, Gy, per_pair, flags);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("serve launch: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
-    if (P == 0) {
-        e = hipMemsetAsync(n_flagged, 0, sizeof(int64_t), s);
-        return e == hipSuccess ? SPHBI_OK : SPHBI_EDEVICE;
-    }
+    if (P == 0) return SPHBI_OK;
     // compact the flagged pairs (pair order)
     hipLaunchKernelGGL(iota64_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, P, w.iota);
     size_t cb = w.cub_bytes;

@@ -173,3 +173,28 @@ def test_binding_fails_loudly_without_library_or_device(monkeypatch):
     with pytest.raises(sb.SphbiError, match="GPU"):
         sb.integrate(0, 1.0, x, x, tri, torch.zeros(1, 2, dtype=torch.float64), torch.zeros(5, dtype=torch.int64),
                      torch.zeros(0, dtype=torch.int32))
+
+
+def test_oversized_launches_rejected_without_device():
+    """Sizes whose grids would not fit a 32-bit thread count are refused with
+    EUNSUPPORTED before any launch (stand-in pointers, never dereferenced)."""
+    L = sb.lib()
+    k = sb.kernel_preset(0)
+    o = sb.opts()
+    z = C.c_void_p(None)
+    host = np.zeros(64, dtype=np.float64)
+    p = C.c_void_p(host.ctypes.data)
+    big = 1 << 28
+    rc = L.sphbi_integrate(C.byref(k), C.byref(o), 1.0, 1, big, p, p, 4, p, p, p, p, 8, p, p, p, z, p, 1 << 20, z)
+    assert rc == -2 and b"particles" in L.sphbi_last_error()
+    rc = L.sphbi_integrate(C.byref(k), C.byref(o), 1.0, 1, 4, p, p, big, p, p, p, p, 8, p, p, p, z, p, 1 << 20, z)
+    assert rc == -2
+    grid, wsb = sb.SphbiGrid(), C.c_size_t(0)
+    rc = L.sphbi_pairlist_plan(big, p, p, 4, p, 1.0, C.byref(grid), C.byref(wsb), z)
+    assert rc == -2
+    rc = L.sphbi_integrate_noalloc(C.byref(k), C.byref(o), 1.0, 1, 4, p, p, sb.NOALLOC_MAX_TRIANGLES + 1, p, p, p,
+                                   p, 8, p, p, p, z, z)
+    assert rc == -2 and b"fixed record array" in L.sphbi_last_error()
+    # the quadrature grid holds 256 // n_gauss particles per block
+    rc = L.sphbi_integrate_quadrature(C.byref(k), 1.0, 1, 64, (1 << 27), p, p, 2, p, p, p, p, 8, p, p, p, z)
+    assert rc == -2 and b"at most" in L.sphbi_last_error()

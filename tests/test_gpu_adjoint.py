@@ -336,3 +336,28 @@ def test_adjoint_4096_sampled_pairs_fd():
     errn = np.abs(dn - refn).max() / np.abs(refn).max()
     say(f"  nodal: scaled err {errn:.2e}")
     assert errn < 1e-13 * 1109.0
+
+
+def test_pairs_outside_the_csr_range_contribute_nothing():
+    """A pair list longer than offsets[-1], or starting after offsets[0] = 0:
+    the pairs outside [offsets[0], offsets[N]) belong to no particle, so the
+    triangle and nodal gradients equal those of the exact list, bit for bit."""
+    say("adjoint stray pairs")
+    wl = W.covering_workload(n_side=64, nx=8, ny=16, seed=4, kernel=W.WENDLAND_C4, field_order=3)
+    t, off, idx, g, tg = setup(wl)
+    ref = sb.integrate_backward(wl.kernel, wl.h, *t, off, idx, *tg)
+    T = wl.n_triangles
+    rng = np.random.default_rng(1)
+    pre = torch.as_tensor(rng.integers(0, T, 50).astype(np.int32), device=DEV)
+    post = torch.as_tensor(rng.integers(0, T, 70).astype(np.int32), device=DEV)
+    idx2 = torch.cat([pre, idx, post])
+    got = sb.integrate_backward(wl.kernel, wl.h, *t, off + 50, idx2, *tg)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+    # no particles at all: nothing reaches the triangles
+    z = torch.zeros(0, dtype=torch.float64, device=DEV)
+    _, _, dtri, dnod = sb.integrate_backward(wl.kernel, wl.h, z, z, t[2], t[3],
+                                             torch.zeros(1, dtype=torch.int64, device=DEV), idx, z, z, z)
+    torch.cuda.synchronize()
+    assert torch.all(dtri == 0) and torch.all(dnod == 0)

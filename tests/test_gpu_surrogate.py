@@ -206,3 +206,24 @@ def test_serve_out_of_range_features_are_flagged():
     out = np.any(np.abs(f[:, :6].astype(np.float32)) > 0.5, axis=1)
     np.testing.assert_array_equal(flags.cpu().numpy().astype(bool), out)
     assert int(nf.cpu()) == int(out.sum())
+
+
+def test_serve_pairs_outside_the_csr_range_are_not_flagged():
+    """Pairs after offsets[-1] belong to no particle: they are never flagged,
+    never evaluated, and the results equal those of the exact list."""
+    wl, px, py, tri, off, idx = mesh_pairs(n_side=32)
+    say("serve stray pairs")
+    p = ref.init_params(5)
+    model = sb.surrogate_pack(dev(p), [0.2, 0.1, -0.1], [0.3, 0.5, 0.5], 1e30)
+    nod = dev(np.ones((1, wl.n_triangles)))
+    P = idx.numel()
+    stray = torch.as_tensor(np.random.default_rng(2).integers(0, wl.n_triangles, 40).astype(np.int32), device=DEV)
+    idx2 = torch.cat([idx, stray])
+    for thr in (-1e30, 1e30):
+        a = sb.surrogate_integrate(0, wl.h, px, py, tri, nod, off, idx, model, thr)
+        b = sb.surrogate_integrate(0, wl.h, px, py, tri, nod, off, idx2, model, thr)
+        torch.cuda.synchronize()
+        for x, y in zip(a[:3], b[:3]):
+            assert torch.equal(x, y)
+        assert int(b[5].cpu()) == int(a[5].cpu()) == (P if thr < 0 else 0)
+        assert int(b[4][P:].sum()) == 0
