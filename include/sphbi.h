@@ -70,6 +70,10 @@ extern "C" {
 #define SPHBI_FP64 0
 #define SPHBI_MIXED 1
 
+#define SPHBI_REFINE_AUTO 0 /* double-double for the pairs the conditioning gate selects (default) */
+#define SPHBI_REFINE_OFF 1  /* every pair in the precision mode alone */
+#define SPHBI_REFINE_ALL 2  /* every pair in double-double (slow; a reference on the device) */
+
 /* Kernel k(q) = sum_p [q < radius[p]] sum_k b[p][k] q^k (q = r/h), with
  * W(r) = c_d h^-2 k(r/h) (Sec. 2: compact polynomial kernels; piecewise
  * kernels such as B-splines are handled piece by piece).  n_pieces 1 or 2,
@@ -83,11 +87,25 @@ typedef struct {
     double c_d;
 } sphbi_kernel;
 
+/* Refinement of ill-conditioned pairs (sphbi_integrate and
+ * sphbi_integrate_noalloc).  For a linear or cubic field the particle-anchored
+ * pieces of the decomposition (Sec. 4) extend the field polynomial from the
+ * triangle to the particle, and its harmonics about the particle (Sec. 3)
+ * exceed the integrand by the factor kappa^order, kappa = d_max l_max /
+ * |2 area| (d_max the farthest vertex from the particle, l_max the longest
+ * edge); FP64 then loses about Kf kappa^order in relative accuracy, Kf =
+ * sum|b_k|/(k+2) / |sum b_k/(k+2)| the cancellation of the kernel's monomial
+ * form (141 for Wendland C2, 1109 C4, 8704 C6, 30 B-spline).  With
+ * SPHBI_REFINE_AUTO the pairs with Kf kappa^order > refine_gate are left out of
+ * the FP64 (or mixed) pass and evaluated in double-double from the input
+ * doubles, then added in pair order; results stay deterministic.  Constant
+ * fields are never refined. */
 typedef struct {
-    int32_t precision; /* SPHBI_FP64 or SPHBI_MIXED */
-    int32_t reserved;
-    double tau_edge;   /* MIXED: pairs whose particle lies within tau_edge*h of an
-                          edge line or vertex are evaluated in FP64 (default 1e-4) */
+    int32_t precision;  /* SPHBI_FP64 or SPHBI_MIXED */
+    int32_t refine;     /* SPHBI_REFINE_AUTO (default), _OFF or _ALL */
+    double tau_edge;    /* MIXED: pairs whose particle lies within tau_edge*h of an
+                           edge line or vertex are evaluated in FP64 (default 1e-4) */
+    double refine_gate; /* threshold on Kf kappa^order; 0 = the precision's default */
 } sphbi_opts;
 
 /* Fills *out with a preset kernel: Wendland C2 (1-q)^4(1+4q), C4

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libsphbi.so")
 
 WENDLAND_C2, WENDLAND_C4, WENDLAND_C6, CUBIC_BSPLINE = 0, 1, 2, 3
 FP64, MIXED = 0, 1
+REFINE_AUTO, REFINE_OFF, REFINE_ALL = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENOWORKSPACE", -5: "ECAPACITY"}
 
 EXPORTS = ["sphbi_kernel_preset", "sphbi_default_opts", "sphbi_last_error", "sphbi_pairlist_plan",
@@ -38,7 +39,8 @@ class SphbiKernel(C.Structure):
 
 
 class SphbiOpts(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("reserved", C.c_int32), ("tau_edge", C.c_double)]
+    _fields_ = [("precision", C.c_int32), ("refine", C.c_int32), ("tau_edge", C.c_double),
+                ("refine_gate", C.c_double)]
 
 
 class SphbiGrid(C.Structure):
@@ -137,11 +139,14 @@ def kernel_preset(kernel_id: int) -> SphbiKernel:
     return k
 
 
-def opts(precision: int = FP64, tau_edge: float = 1e-4) -> SphbiOpts:
+def opts(precision: int = FP64, tau_edge: float = 1e-4, refine: int = REFINE_AUTO,
+         refine_gate: float = 0.0) -> SphbiOpts:
     o = SphbiOpts()
     lib().sphbi_default_opts(C.byref(o))
     o.precision = precision
     o.tau_edge = tau_edge
+    o.refine = refine
+    o.refine_gate = refine_gate
     return o
 
 
@@ -168,11 +173,12 @@ def pairlist(px, py, tri, h: float):
 class Integrator:
     """Holds the kernel description and a reusable workspace for repeated calls."""
 
-    def __init__(self, kernel, h: float, n_nodes: int, precision: int = FP64, tau_edge: float = 1e-4):
+    def __init__(self, kernel, h: float, n_nodes: int, precision: int = FP64, tau_edge: float = 1e-4,
+                 refine: int = REFINE_AUTO, refine_gate: float = 0.0):
         self.kernel = kernel_preset(kernel) if isinstance(kernel, int) else kernel
         self.h = float(h)
         self.n_nodes = int(n_nodes)
-        self.opts = opts(precision, tau_edge)
+        self.opts = opts(precision, tau_edge, refine, refine_gate)
         self.ws = None
 
     def workspace(self, T, device):
@@ -232,7 +238,7 @@ class Integrator:
 
 
 def integrate_noalloc(kernel, h, px, py, tri, nodal, offsets, tri_idx, out, per_pair=None, precision=FP64,
-                      tau_edge=1e-4):
+                      tau_edge=1e-4, refine=REFINE_AUTO, refine_gate=0.0):
     """``sphbi_integrate_noalloc``: :func:`integrate` into caller-provided outputs.
 
     ``out`` = (I, Gx, Gy) float64 [N] device tensors; ``per_pair`` an optional
@@ -251,7 +257,7 @@ def integrate_noalloc(kernel, h, px, py, tri, nodal, offsets, tri_idx, out, per_
         raise SphbiError("outputs must be [N]")
     if per_pair is not None and (_dev(per_pair).shape != (3, P)):
         raise SphbiError("per_pair must be [3, P]")
-    o = opts(precision, tau_edge)
+    o = opts(precision, tau_edge, refine, refine_gate)
     _check(lib().sphbi_integrate_noalloc(C.byref(k), C.byref(o), float(h), nn, N, _ptr(px), _ptr(py), T, _ptr(tri),
                                          _ptr(nodal), _ptr(offsets), _ptr(tri_idx), P, _ptr(I), _ptr(Gx), _ptr(Gy),
                                          _ptr(per_pair), _stream()), "sphbi_integrate_noalloc")
@@ -304,10 +310,11 @@ class BoundaryIntegral(torch.autograd.Function):
         return dpx, dpy, dtri, dnod, None, None, None, None
 
 
-def integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx, per_pair=False, precision=FP64, tau_edge=1e-4):
+def integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx, per_pair=False, precision=FP64, tau_edge=1e-4,
+              refine=REFINE_AUTO, refine_gate=0.0):
     """Per-particle (I, Gx, Gy) [N] (and optionally per-pair [3, P]) on the GPU."""
-    return Integrator(kernel, h, nodal.shape[0], precision, tau_edge)(px, py, tri, nodal, offsets, tri_idx,
-                                                                      per_pair=per_pair)
+    return Integrator(kernel, h, nodal.shape[0], precision, tau_edge, refine, refine_gate)(
+        px, py, tri, nodal, offsets, tri_idx, per_pair=per_pair)
 
 
 # ----------------------------------------------------------------------------

@@ -9,6 +9,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "internal.h"
+#include "refine.h"
 #include "surrogate.h"
 
 namespace sphbi {
@@ -464,9 +465,7 @@ int sphbi_pairlist_fill(int64_t N, const double *px, const double *py, int64_t T
     return SPHBI_OK;
 }
 
-size_t sphbi_integrate_workspace(int64_t T) {
-    return (size_t)(T > 0 ? T : 1) * kRecDoubles * sizeof(double);
-}
+size_t sphbi_integrate_workspace(int64_t T) { return records_bytes(T) + 256; }
 
 static int check_common(const sphbi_kernel *kernel, const sphbi_opts *opts, sphbi_opts *o, double h, int32_t n_nodes,
                         int64_t N, int64_t T, int64_t n_pairs) {
@@ -475,6 +474,11 @@ static int check_common(const sphbi_kernel *kernel, const sphbi_opts *opts, sphb
     sphbi_default_opts(o);
     if (opts) *o = *opts;
     if (o->precision != SPHBI_FP64 && o->precision != SPHBI_MIXED) { set_error("unknown precision %d", o->precision); return SPHBI_EINVAL; }
+    if (o->refine != SPHBI_REFINE_AUTO && o->refine != SPHBI_REFINE_OFF && o->refine != SPHBI_REFINE_ALL) {
+        set_error("unknown refine mode %d", o->refine);
+        return SPHBI_EINVAL;
+    }
+    if (!(o->refine_gate >= 0.0)) { set_error("refine_gate must be >= 0 (0 = default)"); return SPHBI_EINVAL; }
     if (!(o->tau_edge >= 0.0) || !isfinite(o->tau_edge)) { set_error("tau_edge must be finite and >= 0"); return SPHBI_EINVAL; }
     if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
     if (n_nodes != 1 && n_nodes != 3 && n_nodes != 10) { set_error("n_nodes must be 1, 3 or 10"); return SPHBI_EINVAL; }
@@ -486,8 +490,13 @@ static int check_common(const sphbi_kernel *kernel, const sphbi_opts *opts, sphb
     return SPHBI_OK;
 }
 
-int sphbi_field_prepare(double h, int32_t n_nodes, int64_t T, const double *tri, const double *nodal, double *rec,
-                        size_t rec_bytes, void *stream) {
+}  // extern "C"
+
+namespace sphbi {
+
+// sphbi_field_prepare, and zeroing of the refinement counter (nullable)
+static int field_prepare(double h, int32_t n_nodes, int64_t T, const double *tri, const double *nodal, double *rec,
+                         size_t rec_bytes, void *stream, unsigned long long *count) {
     if (!(h > 0.0) || !isfinite(h)) { set_error("h must be positive and finite"); return SPHBI_EINVAL; }
     if (n_nodes != 1 && n_nodes != 3 && n_nodes != 10) { set_error("n_nodes must be 1, 3 or 10"); return SPHBI_EINVAL; }
     if (T < 0) { set_error("negative size"); return SPHBI_EINVAL; }
@@ -500,7 +509,16 @@ int sphbi_field_prepare(double h, int32_t n_nodes, int64_t T, const double *tri,
         return SPHBI_ENOWORKSPACE;
     }
     const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
-    return launch_prepare(order, T, tri, nodal, h, rec, (hipStream_t)stream);
+    return launch_prepare(order, T, tri, nodal, h, rec, (hipStream_t)stream, count);
+}
+
+}  // namespace sphbi
+
+extern "C" {
+
+int sphbi_field_prepare(double h, int32_t n_nodes, int64_t T, const double *tri, const double *nodal, double *rec,
+                        size_t rec_bytes, void *stream) {
+    return field_prepare(h, n_nodes, T, tri, nodal, rec, rec_bytes, stream, nullptr);
 }
 
 int sphbi_integrate_prepared(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes,
@@ -519,13 +537,74 @@ int sphbi_integrate_prepared(const sphbi_kernel *kernel, const sphbi_opts *opts,
     int deg = 0;
     const KArgs K = make_kargs(kernel, &deg);
     const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
-    return launch_forward(order, deg, o.precision, o.tau_edge, K, h, N, px, py, offsets, tri_idx, n_pairs, T, rec, I,
-                          Gx, Gy, per_pair, (hipStream_t)stream);
+    return launch_forward(order, deg, o.precision, o.tau_edge, K, refine_off(), h, N, px, py, offsets, tri_idx,
+                          n_pairs, T, rec, I, Gx, Gy, per_pair, (hipStream_t)stream);
 }
 
 }  // extern "C"
 
 namespace sphbi {
+
+// Default thresholds of the conditioning gate on Kf kappa^order (see
+// sphbi_opts), G = G0 (141 / Kf)^1.25, 141 being Kf of Wendland C2.  Fitted
+// to the per-particle errors measured against the double-double path on
+// covering meshes (aspect ratio 20, cubic and linear fields) and on 0.5-degree
+// slivers with particles 1e-8..1e-2 h from edges and vertices: with
+// G0 = 3e6 the FP64 pass stays within 1e-12 of the scale for Wendland C2, C4
+// and C6 (the Wendland C2 covering mesh of 2^20 particles has no pair above
+// it); with G0 = 1e9 the mixed pass stays within 1e-6.
+constexpr double kGateFP64 = 3e6, kGateMixed = 1e9;
+
+// Kf = sum_p sum_k |b_pk| R_p^(k+2)/(k+2) / |sum_p sum_k b_pk R_p^(k+2)/(k+2)|:
+// the cancellation of the kernel's monomial form in the integral over the
+// support disc.
+static double kernel_cancellation(const KArgs &K) {
+    double sa = 0.0, s = 0.0;
+    for (int p = 0; p < K.npieces; ++p)
+        for (int k = 0; k <= kMaxDeg; ++k) {
+            const double t = K.b[p][k] * pow(K.R[p], k + 2) / (k + 2);
+            sa += fabs(t);
+            s += t;
+        }
+    return s != 0.0 ? sa / fabs(s) : INFINITY;
+}
+
+RefineGate make_gate(const sphbi_opts &o, int order, const KArgs &K) {
+    if (o.refine != SPHBI_REFINE_AUTO || order == 0) return refine_off();
+    const double kf = kernel_cancellation(K);
+    const double thr = o.refine_gate > 0.0 ? o.refine_gate
+                                           : (o.precision == SPHBI_MIXED ? kGateMixed : kGateFP64) * pow(141.0 / kf, 1.25);
+    if (!isfinite(thr)) return refine_off();
+    const double g = thr / kf;
+    return RefineGate{order, 0, g * g};
+}
+
+int integrate_run(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,
+                  const double *px, const double *py, int64_t T, const double *tri, const double *nodal, double *rec,
+                  size_t rec_bytes, const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, double *I,
+                  double *Gx, double *Gy, double *per_pair, void *stream) {
+    sphbi_opts o;
+    sphbi_default_opts(&o);
+    if (opts) o = *opts;
+    int deg = 0;
+    const KArgs K = make_kargs(kernel, &deg);
+    const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
+    hipStream_t s = (hipStream_t)stream;
+    if (o.refine == SPHBI_REFINE_ALL)
+        return launch_refine(order, deg, K, refine_off(), true, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, I,
+                             Gx, Gy, per_pair, s);
+    // the refinement counter sits behind the records
+    unsigned long long *count = (unsigned long long *)((char *)rec + records_bytes(T));
+    RefineGate gate = T > 0 ? make_gate(o, order, K) : refine_off();
+    gate.count = count;
+    int rc = field_prepare(h, n_nodes, T, tri, nodal, rec, rec_bytes, stream, gate.order ? count : nullptr);
+    if (rc) return rc;
+    rc = launch_forward(order, deg, o.precision, o.tau_edge, K, gate, h, N, px, py, offsets, tri_idx, n_pairs, T, rec,
+                        I, Gx, Gy, per_pair, s);
+    if (rc || !gate.order) return rc;
+    return launch_refine(order, deg, K, gate, false, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, I, Gx, Gy,
+                         per_pair, s);
+}
 
 int check_integrate_args(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,
                          const double *px, const double *py, int64_t T, const double *tri, const double *nodal,
@@ -559,10 +638,8 @@ int sphbi_integrate(const sphbi_kernel *kernel, const sphbi_opts *opts, double h
         set_error("workspace too small (%zu < %zu)", ws_bytes, sphbi_integrate_workspace(T));
         return SPHBI_ENOWORKSPACE;
     }
-    rc = sphbi_field_prepare(h, n_nodes, T, tri, nodal, (double *)ws, ws_bytes, stream);
-    if (rc) return rc;
-    return sphbi_integrate_prepared(kernel, opts, h, n_nodes, N, px, py, T, (const double *)ws, offsets, tri_idx,
-                                    n_pairs, I, Gx, Gy, per_pair, stream);
+    return integrate_run(kernel, opts, h, n_nodes, N, px, py, T, tri, nodal, (double *)ws, ws_bytes, offsets, tri_idx,
+                         n_pairs, I, Gx, Gy, per_pair, stream);
 }
 
 int sphbi_integrate_quadrature(const sphbi_kernel *kernel, double h, int32_t n_nodes, int32_t n_gauss, int64_t N,

@@ -63,6 +63,7 @@
 
 #include "internal.h"
 #include "pairmath.h"
+#include "refine.h"
 
 namespace sphbi {
 namespace {
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(64, fwd_waves(DEG, ORDER, MIXED)) void forward_kern
                                                       double *__restrict__ Gx, double *__restrict__ Gy,
                                                       double *__restrict__ per_pair, int64_t P, int64_t T,
                                                       const double *__restrict__ rec2,
-                                                      const double *__restrict__ gam) {
+                                                      const double *__restrict__ gam, const RefineGate gate) {
     const int lane = threadIdx.x & 63;
     const int64_t p0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
     if (p0 >= N) return;                               // whole wavefront
@@ -168,7 +169,22 @@ __global__ __launch_bounds__(64, fwd_waves(DEG, ORDER, MIXED)) void forward_kern
         double vI = 0.0, vX = 0.0, vY = 0.0;
         if (q < q_end) {
             const int32_t t = tri_idx[q];
-            if (t >= 0 && t < T) {   // out-of-range triangle indices contribute nothing
+            bool skip = false;      // a pair the refinement pass evaluates in double-double
+            if (FM == kFieldPlain && ORDER >= 1 && gate.order && t >= 0 && t < T) {
+                const double *r = rec + (int64_t)t * kRecDoubles;
+                double gx[3], gy[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    gx[k] = (r[2 * k] - px[ip]) * invh;
+                    gy[k] = (r[2 * k + 1] - py[ip]) * invh;
+                }
+                skip = gate.fires(gx, gy);
+            }
+            if (FM == kFieldPlain && ORDER >= 1 && gate.order) {
+                const unsigned long long nskip = __popcll(__ballot(skip));
+                if (lane == 0 && nskip) atomicAdd(gate.count, nskip);
+            }
+            if (t >= 0 && t < T && !skip) {   // out-of-range triangle indices contribute nothing
                 const double *r = rec + (int64_t)t * kRecDoubles;
                 constexpr int EU = fwd_edge_unroll(DEG, ORDER);
                 [[maybe_unused]] double rc[FM == kFieldComb ? kRecDoubles : 1];
@@ -182,7 +198,7 @@ __global__ __launch_bounds__(64, fwd_waves(DEG, ORDER, MIXED)) void forward_kern
                 else pair_fwd<DEG, ORDER, double, ExactMath, EU>(K, ExactMath(), 0.0, px[ip], py[ip], invh, r, vI, vX,
                                                                  vY);
             }
-            if (per_pair) {
+            if (per_pair && !skip) {
                 per_pair[q] = vI;
                 per_pair[P + q] = vX;
                 per_pair[2 * P + q] = vY;
@@ -237,7 +253,7 @@ __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_wav
     const KArgs K, double tau, double invh, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
     const int64_t *__restrict__ off, const int32_t *__restrict__ tri_idx, const double *__restrict__ rec,
     double *__restrict__ I, double *__restrict__ Gx, double *__restrict__ Gy, double *__restrict__ per_pair, int64_t P,
-    int64_t T, const double *__restrict__ rec2, const double *__restrict__ gam) {
+    int64_t T, const double *__restrict__ rec2, const double *__restrict__ gam, const RefineGate gate) {
     __shared__ double s_res[SW][3];
     __shared__ uint16_t s_perm[SW];
     __shared__ uint8_t s_own[SW];
@@ -281,6 +297,16 @@ __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_wav
                         ay[k] = (r[2 * k + 1] - y) * invh;
                     }
                     near = near_edges(ax, ay, R2, rot);
+                    // a pair the refinement pass evaluates in double-double:
+                    // no work here (key bit 4), sorted with the cheapest
+                    if (FM == kFieldPlain && ORDER >= 1 && gate.order && gate.fires(ax, ay)) {
+                        near = 0;
+                        rot = 16;
+                    }
+                }
+                if (FM == kFieldPlain && ORDER >= 1 && gate.order) {
+                    const unsigned long long nskip = __popcll(__ballot(rot == 16));
+                    if (lane == 0 && nskip) atomicAdd(gate.count, nskip);
                 }
                 s_own[i] = (uint8_t)lo;
                 s_key[i] = (uint8_t)(near << 2 | rot);
@@ -308,7 +334,7 @@ __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_wav
 #pragma unroll
         for (int b = 0; b < 4; ++b) run[b] = start[b] + (int)(pre >> (16 * b) & 0xffff);
         for (int i = lane; i < n; i += 64) {
-            const int b = s_key[i] >> 2;
+            const int b = (s_key[i] >> 2) & 3;
             int pos = run[0];
 #pragma unroll
             for (int bb = 1; bb < 4; ++bb)
@@ -330,7 +356,8 @@ __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_wav
                 const int64_t ip = p0 + own < N ? p0 + own : N - 1;
                 double vI = 0.0, vX = 0.0, vY = 0.0;
                 const int32_t t = tri_idx[q];
-                if (t >= 0 && t < T) {
+                const bool skip = key & 16;
+                if (t >= 0 && t < T && !skip) {
                     const double *r = rec + (int64_t)t * kRecDoubles;
                     if constexpr (FM == kFieldDivCurl) {
                         pair_div_curl_rot<DEG, ORDER>(K, px[ip], py[ip], invh, r, rec2 + (int64_t)t * kRecDoubles,
@@ -355,7 +382,7 @@ __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_wav
                         }
                     }
                 }
-                if (per_pair) {
+                if (per_pair && !skip) {
                     per_pair[q] = vI;
                     per_pair[P + q] = vX;
                     per_pair[2 * P + q] = vY;
@@ -403,6 +430,7 @@ struct FwdArgs {
     double *I, *Gx, *Gy, *per_pair;
     int64_t P, T;
     const double *rec2, *gam;      // combined fields only
+    RefineGate gate;               // plain fields: pairs left to the refinement pass
 };
 
 // Both kernels run one wavefront (64 particles) per block.
@@ -413,11 +441,11 @@ void launch_fwd_t(const KArgs &K, const FwdArgs &a, hipStream_t s) {
     if constexpr (fwd_sorted(DEG, ORDER) || FM == kFieldDivCurl || FM == kFieldPairWeight)
         hipLaunchKernelGGL((forward_sorted_kernel<DEG, ORDER, MIXED, SW, FM>), dim3((unsigned)waves), dim3(64), 0,
                            s, K, a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair,
-                           a.P, a.T, a.rec2, a.gam);
+                           a.P, a.T, a.rec2, a.gam, a.gate);
     else
         hipLaunchKernelGGL((forward_kernel<DEG, ORDER, MIXED, FM>), dim3((unsigned)waves), dim3(64), 0, s, K,
                            a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair, a.P,
-                           a.T, a.rec2, a.gam);
+                           a.T, a.rec2, a.gam, a.gate);
 }
 
 template <int ORDER, bool MIXED, int FM = kFieldPlain>

@@ -55,9 +55,21 @@ int check_integrate_args(const sphbi_kernel *kernel, const sphbi_opts *opts, dou
                          const double *Gx, const double *Gy, const double *per_pair);
 KArgs make_kargs(const sphbi_kernel *k, int *deg_out);
 
+// count (nullable): zeroed by the launch (the refinement counter that the
+// next forward pass adds to)
 int launch_prepare(int order, int64_t T, const double *tri, const double *nodal, double h, double *rec,
-                   hipStream_t s);
-int launch_forward(int order, int deg, int precision, double tau_edge, const KArgs &K, double h, int64_t N,
+                   hipStream_t s, unsigned long long *count = nullptr);
+// bytes of the record buffer of T triangles; the refinement counter follows
+inline size_t records_bytes(int64_t T) { return (((size_t)(T > 0 ? T : 1) * kRecDoubles * sizeof(double)) + 255) & ~(size_t)255; }
+struct RefineGate;
+// the whole forward call on prepared-record storage rec: records, FP64 or
+// mixed pass, and the double-double refinement the options ask for
+int integrate_run(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,
+                  const double *px, const double *py, int64_t T, const double *tri, const double *nodal, double *rec,
+                  size_t rec_bytes, const int64_t *offsets, const int32_t *tri_idx, int64_t n_pairs, double *I,
+                  double *Gx, double *Gy, double *per_pair, void *stream);
+int launch_forward(int order, int deg, int precision, double tau_edge, const KArgs &K, const RefineGate &gate,
+                   double h, int64_t N,
                    const double *px, const double *py, const int64_t *offsets, const int32_t *tri_idx,
                    int64_t P, int64_t T, const double *rec, double *I, double *Gx, double *Gy, double *per_pair,
                    hipStream_t s);

@@ -17,8 +17,10 @@ namespace {
 constexpr int64_t kNoAllocMaxT = SPHBI_NOALLOC_MAX_TRIANGLES;
 constexpr int kMaxDevices = 64;
 
-// Field records of at most kNoAllocMaxT triangles (16 MiB).
-__device__ __align__(256) double scratch[kNoAllocMaxT * kRecDoubles];
+// Field records of at most kNoAllocMaxT triangles (16 MiB) and the
+// refinement counter behind them (the layout of sphbi_integrate's workspace).
+constexpr size_t kScratchDoubles = kNoAllocMaxT * kRecDoubles + 32;
+__device__ __align__(256) double scratch[kScratchDoubles];
 
 std::mutex g_mu;
 void *g_ptr[kMaxDevices] = {};
@@ -65,11 +67,9 @@ extern "C" int sphbi_integrate_noalloc(const sphbi_kernel *kernel, const sphbi_o
     double *rec = nullptr;
     rc = scratch_ptr(&rec);
     if (rc) return rc;
-    const size_t bytes = (size_t)kNoAllocMaxT * kRecDoubles * sizeof(double);
-    if (T > 0) {
-        rc = sphbi_field_prepare(h, n_nodes, T, tri, nodal, rec, bytes, stream);
-        if (rc) return rc;
-    }
-    return sphbi_integrate_prepared(kernel, opts, h, n_nodes, N, px, py, T, rec, offsets, tri_idx, n_pairs, I, Gx, Gy,
-                                    per_pair, stream);
+    const size_t bytes = kScratchDoubles * sizeof(double);
+    static_assert(kScratchDoubles * sizeof(double) >= kNoAllocMaxT * kRecDoubles * sizeof(double) + 256,
+                  "records and counter must fit");
+    return integrate_run(kernel, opts, h, n_nodes, N, px, py, T, tri, nodal, rec, bytes, offsets, tri_idx, n_pairs, I,
+                         Gx, Gy, per_pair, stream);
 }

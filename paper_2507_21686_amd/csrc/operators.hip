@@ -153,8 +153,8 @@ int launch_operator(int op, int order, int deg, const KArgs &K, double h, int64_
     }
     const unsigned nb = (unsigned)((N + 255) / 256);
     if (op == kNormal) {
-        int rc = launch_forward(0, deg, SPHBI_FP64, 0.0, K, h, N, px, py, off, tri_idx, P, T, rec, Ib, out_a, out_b,
-                                nullptr, s);
+        int rc = launch_forward(0, deg, SPHBI_FP64, 0.0, K, refine_off(), h, N, px, py, off, tri_idx, P, T, rec, Ib,
+                                out_a, out_b, nullptr, s);
         if (rc) return rc;
     } else if (op == kDivCurl) {
         const FwdArgs a{0.0, invh, N, px, py, off, tri_idx, rec, Ib, out_a, out_b, nullptr, P, T, rec2, nullptr};

@@ -1,11 +1,14 @@
-// Closed-form pair mathematics shared by the forward and adjoint kernels
-// (scalar type S is double throughout; the precision policy M decides how the
-// square roots, reciprocals and angles are evaluated).  See forward.hip for the
-// derivation.
+// Closed-form pair mathematics shared by the forward and adjoint kernels.
+// The scalar type S is double, or the double-double type of ddmath.h for the
+// ill-conditioned pairs; the precision policy M decides how the square
+// roots, reciprocals, angles and logarithms are evaluated, and the kernel
+// description K (KArgs, or KArgsDD for double-double) supplies the kernel's
+// coefficients.  See forward_pair.h for the derivation.
 #pragma once
 
 #include <math.h>
 
+#include "ddmath.h"
 #include "internal.h"
 #include "precision.h"
 
@@ -20,6 +23,47 @@ __device__ inline double lit(double c) {
     const double a = fabs(c);
     return (a == 0.0 || a == 0.5 || a == 1.0 || a == 2.0 || a == 4.0) ? c : sconst(c);
 }
+
+// 1/n for a small integer n in the scalar type of a pair: an FP64 constant
+// handed over like lit(), or the double-double nearest to 1/n.
+template <typename S>
+struct RecipInt {
+    __device__ static double get(int n) { return lit(1.0 / n); }
+};
+template <>
+struct RecipInt<dd> {
+    __host__ __device__ static dd get(int n) { return dd_recip(n); }
+};
+
+// The kernel coefficients of a piece, for field degree m (see KArgs):
+// b_k / (k + 2 + m), k b_k / (k + 1 + m) and the unit-sector integrals.
+__device__ inline double coef_bq(const KArgs &K, int pc, int m, int k) { return K.bq[pc][m][k]; }
+__device__ inline double coef_kbq(const KArgs &K, int pc, int m, int k) { return K.kbq[pc][m][k]; }
+__device__ inline double coef_sv(const KArgs &K, int pc, int m) { return K.sv[pc][m]; }
+__device__ inline double coef_sw(const KArgs &K, int pc, int m) { return K.sw[pc][m]; }
+
+// Double-double kernel description: the monomial coefficients b exactly as
+// given, the quotients formed in double-double where they are used, the
+// unit-sector integrals in double-double (made on the host by
+// make_kargs_dd).
+struct KArgsDD {
+    int npieces;
+    int pad;
+    double R[2];
+    double iR[2];
+    double b[2][kMaxDeg + 1];
+    dd sv[2][kMaxOrder + 1];
+    dd sw[2][kMaxOrder + 1];
+    double cd;
+};
+__host__ __device__ inline dd coef_bq(const KArgsDD &K, int pc, int m, int k) {
+    return K.b[pc][k] * dd_recip(k + 2 + m);
+}
+__host__ __device__ inline dd coef_kbq(const KArgsDD &K, int pc, int m, int k) {
+    return (K.b[pc][k] * (double)k) * dd_recip(k + 1 + m);
+}
+__host__ __device__ inline dd coef_sv(const KArgsDD &K, int pc, int m) { return K.sv[pc][m]; }
+__host__ __device__ inline dd coef_sw(const KArgsDD &K, int pc, int m) { return K.sw[pc][m]; }
 
 // Chebyshev coefficients: T_n(x) = sum_j chebT(n,j) x^j, U_n likewise.
 __host__ __device__ constexpr double chebT(int n, int j) {
@@ -272,11 +316,13 @@ template <typename S, int NF = 1>
 struct FieldSink {
     static constexpr int kHMax = 0, kPMax = 0;
     static constexpr bool kOnLine = false;
-    __host__ __device__ void radial(const KArgs &, int, S, const S *, const S *) {}
+    template <typename KA>
+    __host__ __device__ void radial(const KA &, int, S, const S *, const S *) {}
     const Harm<S> *hv[NF];          // NF fields sharing the geometry
     S I[NF], X[NF], Y[NF];
     Harm<S> hx[NF], hy[NF];
-    __host__ __device__ void sector(int m, double sv, double sw, const S *angc, const S *angs) {
+    template <typename C>
+    __host__ __device__ void sector(int m, C sv, C sw, const S *angc, const S *angs) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             Harm<S> gx, gy;
@@ -316,9 +362,11 @@ template <int ORDER, typename S>
 struct BasisSink {
     static constexpr int kHMax = 0, kPMax = 0;
     static constexpr bool kOnLine = false;
-    __host__ __device__ void radial(const KArgs &, int, S, const S *, const S *) {}
+    template <typename KA>
+    __host__ __device__ void radial(const KA &, int, S, const S *, const S *) {}
     Harm<S> vb[ORDER + 1], gb[ORDER + 1];
-    __host__ __device__ void sector(int m, double sv, double sw, const S *angc, const S *angs) {
+    template <typename C>
+    __host__ __device__ void sector(int m, C sv, C sw, const S *angc, const S *angs) {
 #pragma unroll
         for (int n = m & 1; n <= m; n += 2) {
             vb[m].c[n] += sv * angc[n];
@@ -493,7 +541,8 @@ struct LineSink {
     static constexpr bool kOnLine = true;
     LineSums<DEG, ORDER, S> ln;
     __device__ void radial(const KArgs &K, int pc, S, const S *H, const S *P) { ln.add(K, pc, H, P); }
-    __device__ void sector(int, double, double, const S *, const S *) {}
+    template <typename C>
+    __device__ void sector(int, C, C, const S *, const S *) {}
     __device__ void begin(int) {}
     __device__ void value(int, int, S, S) {}
     __device__ void grad(int, int, S, S) {}
@@ -503,8 +552,8 @@ struct LineSink {
 // ra2, rb2 are the squared distances of the edge's ends from the particle: an
 // end is clipped (outside the circle) by the same test in both edges that
 // share it, which the sector terms below rely on.
-template <int DEG, int ORDER, typename S, typename M, typename Sink>
-__host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc, S p, S ya, S yb, S ra2, S rb2,
+template <int DEG, int ORDER, typename S, typename KA, typename M, typename Sink>
+__host__ __device__ inline void edge_piece(const KA &K, const M &math, int pc, S p, S ya, S yb, S ra2, S rb2,
                                            Sink &sink) {
     constexpr int HMAX = DEG + ORDER + 1 > Sink::kHMax ? DEG + ORDER + 1 : Sink::kHMax;
     constexpr int PMAX = DEG + ORDER > Sink::kPMax ? DEG + ORDER : Sink::kPMax;
@@ -542,14 +591,14 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
         S dn1 = 1.0, tn1 = 0.0, dn = cpc, tn = spc;        // cos/sin of n psi_c
 #pragma unroll
         for (int n = 1; n <= ORDER + 1; ++n) {
-            const double inv = lit(1.0 / n);
+            const auto inv = RecipInt<S>::get(n);
             angc[n] -= tn * (wc * inv);
             angs[n] += dn * (ws * inv);
             const S dn2 = 2.0 * cpc * dn - dn1, tn2 = 2.0 * cpc * tn - tn1;
             dn1 = dn; tn1 = tn; dn = dn2; tn = tn2;
         }
 #pragma unroll
-        for (int m = 0; m <= ORDER; ++m) sink.sector(m, K.sv[pc][m], K.sw[pc][m], angc, angs);
+        for (int m = 0; m <= ORDER; ++m) sink.sector(m, coef_sv(K, pc, m), coef_sw(K, pc, m), angc, angs);
     }
 
     // ---- triangle parts: radial 2F1 terms H_c and powers P_e
@@ -571,12 +620,12 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
         for (int c = 2; c <= HMAX; ++c) {
             gA *= rA;
             gB *= rB;
-            H[c] = (gB * yB - gA * yA + lit(c - 1.0) * p2 * H[c - 2]) * lit(1.0 / c);
+            H[c] = (gB * yB - gA * yA + lit(c - 1.0) * p2 * H[c - 2]) * RecipInt<S>::get(c);
         }
         S qA = rA, qB = rB;            // rho^{e+1}
 #pragma unroll
         for (int e = 0; e <= PMAX; ++e) {
-            P[e] = (qB - qA) * lit(1.0 / (e + 1));
+            P[e] = (qB - qA) * RecipInt<S>::get(e + 1);
             qA *= rA;
             qB *= rB;
         }
@@ -597,28 +646,28 @@ __host__ __device__ inline void edge_piece(const KArgs &K, const M &math, int pc
         for (int j = 0; j <= m; ++j) {
             S s = 0.0;
 #pragma unroll
-            for (int k = 0; k <= DEG; ++k) s = fma(K.bq[pc][m][k], H[k + 1 + m - j], s);
+            for (int k = 0; k <= DEG; ++k) s = fma(coef_bq(K, pc, m, k), H[k + 1 + m - j], s);
             Ac[j] = s;
         }
 #pragma unroll
         for (int j = 0; j < m; ++j) {
             S s = 0.0;
 #pragma unroll
-            for (int k = 0; k <= DEG; ++k) s = fma(K.bq[pc][m][k], P[k + m - j], s);
+            for (int k = 0; k <= DEG; ++k) s = fma(coef_bq(K, pc, m, k), P[k + m - j], s);
             As[j] = s;
         }
 #pragma unroll
         for (int j = 0; j <= m + 1; ++j) {
             S s = 0.0;
 #pragma unroll
-            for (int k = 1; k <= DEG; ++k) s = fma(K.kbq[pc][m][k], H[k + m - j], s);
+            for (int k = 1; k <= DEG; ++k) s = fma(coef_kbq(K, pc, m, k), H[k + m - j], s);
             Bc[j] = s;
         }
 #pragma unroll
         for (int j = 0; j <= m; ++j) {
             S s = 0.0;
 #pragma unroll
-            for (int k = 1; k <= DEG; ++k) s = fma(K.kbq[pc][m][k], P[k + m - 1 - j], s);
+            for (int k = 1; k <= DEG; ++k) s = fma(coef_kbq(K, pc, m, k), P[k + m - 1 - j], s);
             Bs[j] = s;
         }
         // value harmonics n = m, m-2, ...
@@ -690,8 +739,8 @@ __host__ __device__ inline void edge_phases(S nx, S ny, S *cph, S *sph) {
 // of the value and the gradient integrand, F_c = sin(n theta)/n and
 // F_s = -cos(n theta)/n, summed over the pieces that clip the vertex), in the
 // triangle's frame.  (vx, vy): vertex relative to the particle, units of h.
-template <int ORDER, typename S, typename M>
-__host__ __device__ inline void vertex_ray_terms(const KArgs &K, const M &math, const Harm<S> *hg, S vx, S vy, double s,
+template <int ORDER, typename S, typename KA, typename M>
+__host__ __device__ inline void vertex_ray_terms(const KA &K, const M &math, const Harm<S> *hg, S vx, S vy, double s,
                                                  S &oI, S &oX, S &oY) {
     const S r2 = vx * vx + vy * vy;
     if (!(r2 > 0.0)) return;
@@ -703,7 +752,7 @@ __host__ __device__ inline void vertex_ray_terms(const KArgs &K, const M &math, 
         fc[0] = fs[0] = 0.0;
 #pragma unroll
         for (int n = 1; n <= ORDER + 1; ++n) {
-            const double inv = lit(1.0 / n);
+            const auto inv = RecipInt<S>::get(n);
             fc[n] = sn * inv;
             fs[n] = -cn * inv;
             const S cn2 = 2.0 * c1 * cn - cn1, sn2 = 2.0 * c1 * sn - sn1;
@@ -728,9 +777,9 @@ __host__ __device__ inline void vertex_ray_terms(const KArgs &K, const M &math, 
                     ty += gy.c[n] * fc[n] + gy.s[n] * fs[n];
                 }
             }
-            vi += K.sv[pc][m] * ti;
-            vxs += K.sw[pc][m] * tx;
-            vys += K.sw[pc][m] * ty;
+            vi += coef_sv(K, pc, m) * ti;
+            vxs += coef_sw(K, pc, m) * tx;
+            vys += coef_sw(K, pc, m) * ty;
         }
         oI += s * vi;
         oX += s * vxs;
@@ -740,13 +789,13 @@ __host__ __device__ inline void vertex_ray_terms(const KArgs &K, const M &math, 
 
 // tau: edges whose line passes within tau (units of h) of the particle are
 // evaluated with the exact policy (only meaningful for MixedMath).
-template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL = 3>
-__host__ __device__ inline void pair_core(const KArgs &K, const M &math, double tau, const S *ax, const S *ay,
+template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL = 3, typename KA>
+__host__ __device__ inline void pair_core(const KA &K, const M &math, double tau, const S *ax, const S *ay,
                                           const S &area2, const S *c, double invh, S &oI, S &oX, S &oY);
 
 // One pair: particle (x, y), record r (vertices and field about vertex 0).
-template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL = 3>
-__host__ __device__ inline void pair_fwd(const KArgs &K, const M &math, double tau, S x, S y, double invh,
+template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL = 3, typename KA>
+__host__ __device__ inline void pair_fwd(const KA &K, const M &math, double tau, S x, S y, double invh,
                                          const S *__restrict__ r, S &oI, S &oX, S &oY) {
     oI = oX = oY = 0.0;
     S ax[3], ay[3];
@@ -784,8 +833,8 @@ __host__ __device__ inline int near_edges(const double *ax, const double *ay, do
 // integrals do not depend on where the edge loop starts, and a common start
 // lets the lanes of a wavefront take the same branches (see the sorted
 // forward kernel).
-template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL = 3>
-__host__ __device__ inline void pair_fwd_rot(const KArgs &K, const M &math, double tau, S x, S y, double invh,
+template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL = 3, typename KA>
+__host__ __device__ inline void pair_fwd_rot(const KA &K, const M &math, double tau, S x, S y, double invh,
                                              const S *__restrict__ r, int rot, S &oI, S &oX, S &oY) {
     oI = oX = oY = 0.0;
     S ax[3], ay[3];
@@ -814,8 +863,8 @@ __host__ __device__ inline void pair_fwd_rot(const KArgs &K, const M &math, doub
 // (non-zero).  The fields share every geometric term; only the contraction
 // with each field's harmonics is repeated.  EDGE_UNROLL = 1 keeps the edge
 // loop rolled (one edge's state live at a time), 3 unrolls it.
-template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL, int NF>
-__host__ __device__ inline void pair_core_n(const KArgs &K, const M &math, double tau, const S *ax, const S *ay,
+template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL, int NF, typename KA>
+__host__ __device__ inline void pair_core_n(const KA &K, const M &math, double tau, const S *ax, const S *ay,
                                             const S &area2, const S *c, double invh, S *oI, S *oX, S *oY) {
     Harm<S> hg[NF][ORDER + 1];
 #pragma unroll
@@ -893,8 +942,8 @@ __host__ __device__ inline void pair_core_n(const KArgs &K, const M &math, doubl
 }
 
 // The pair for one field.
-template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL>
-__host__ __device__ inline void pair_core(const KArgs &K, const M &math, double tau, const S *ax, const S *ay,
+template <int DEG, int ORDER, typename S, typename M, int EDGE_UNROLL, typename KA>
+__host__ __device__ inline void pair_core(const KA &K, const M &math, double tau, const S *ax, const S *ay,
                                           const S &area2, const S *c, double invh, S &oI, S &oX, S &oY) {
     pair_core_n<DEG, ORDER, S, M, EDGE_UNROLL, 1>(K, math, tau, ax, ay, area2, c, invh, &oI, &oX, &oY);
 }

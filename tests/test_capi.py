@@ -81,7 +81,9 @@ def test_bad_arguments_rejected_without_device():
 
 
 def test_workspace_size():
-    assert sb.lib().sphbi_integrate_workspace(1000) == 1000 * 16 * 8
+    # 128 B records per triangle (rounded up to 256 B), then 256 B for the refinement counter
+    assert sb.lib().sphbi_integrate_workspace(1000) == 1000 * 16 * 8 + 256
+    assert sb.lib().sphbi_integrate_workspace(1001) == 1002 * 16 * 8 + 256
     assert sb.lib().sphbi_integrate_workspace(0) >= 8
 
 
