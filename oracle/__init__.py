@@ -27,6 +27,10 @@ SOURCES = ["definition.c", "closed_form.c"]
 _lib = None
 
 
+class OracleCapped(ValueError):
+    """The definition oracle's adaptive rule stopped at its depth or call cap."""
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle sources with gcc (OpenMP) into ``oracle/liboracle.so``."""
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
@@ -96,7 +100,9 @@ def pair(kernel_id, h, px, py, tri6, A, method="definition"):
     out = np.zeros(3)
     fn = lib().oracle_pair if method == "definition" else lib().oracle_cf_pair
     rc = fn(int(kernel_id), float(h), int(A.shape[0]), float(px), float(py), _p(tri6), _p(A), _p(out))
-    if rc:
+    if rc > 0 and method == "definition":
+        raise OracleCapped("the adaptive rule reached its depth or call cap: the pair is unverified")
+    if rc < 0:
         raise ValueError(f"oracle pair failed ({rc})")
     return out
 
@@ -127,7 +133,9 @@ def integrate(kernel_id, h, px, py, tri, nodal, offsets, tri_idx, per_pair=False
     rc = fn(int(kernel_id), float(h), int(nodal.shape[0]), N, _p(px), _p(py), T, _p(tri), _p(nodal),
             _p(offsets), _p(tri_idx), _p(I), _p(Gx), _p(Gy), _p(pp) if pp is not None else None,
             int(nthreads))
-    if rc:
+    if rc > 0 and method == "definition":
+        raise OracleCapped(f"the adaptive rule reached its depth or call cap on {rc} pairs: unverified")
+    if rc < 0:
         raise ValueError(f"oracle integrate failed ({rc})")
     return (I, Gx, Gy, pp) if per_pair else (I, Gx, Gy)
 

@@ -236,6 +236,7 @@ typedef struct {
     int nr;                 /* radial GL points */
     long calls;
     double tol;
+    int capped;             /* an interval was accepted at a cap, not by its error estimate */
 } octx;
 
 /* value, and radial part of the gradient (before the -e_theta factor) */
@@ -308,14 +309,17 @@ static void glq(const octx *c, double a, double b, int n, double q[3], double *q
  * angle (r_in and r_out come from ratios that are ill-conditioned for rays
  * nearly parallel to an edge), so a tighter tolerance would only refine
  * noise; the total error stays below 2.5e-14 times the field scale.  Depth
- * and call caps bound the work. */
+ * and call caps bound the work; an interval accepted at a cap marks the pair
+ * as unverified (the entry points report it). */
 static void adapt(octx *c, double a, double b, int depth, double acc[3]) {
     double q1[3], q2[3];
     glq(c, a, b, 10, q1, NULL);
     glq(c, a, b, 20, q2, NULL);
     double err = 0.0;
     for (int k = 0; k < 3; ++k) { double d = fabs(q2[k] - q1[k]); if (d > err) err = d; }
-    if (err <= c->tol * (b - a) || depth >= 40 || ++c->calls > 2000000) {
+    const int converged = err <= c->tol * (b - a);
+    if (converged || depth >= 40 || ++c->calls > 2000000) {
+        if (!converged) c->capped = 1;
         acc[0] += q2[0]; acc[1] += q2[1]; acc[2] += q2[2];
         return;
     }
@@ -329,11 +333,13 @@ static int cmp_d(const void *a, const void *b) {
     return (x > y) - (x < y);
 }
 
-/* One pair in the normalised frame.  out = (int A k, -int A e k' ) without C_d. */
-static void pair_normalised(const okern *K, otri *t, double out[3]) {
+/* One pair in the normalised frame.  out = (int A k, -int A e k' ) without C_d.
+ * Returns 1 when the adaptive rule stopped at a cap somewhere (the value is
+ * then not verified to the stated tolerance), else 0. */
+static int pair_normalised(const okern *K, otri *t, double out[3]) {
     out[0] = out[1] = out[2] = 0.0;
     double area2 = (t->x[1] - t->x[0]) * (t->y[2] - t->y[0]) - (t->x[2] - t->x[0]) * (t->y[1] - t->y[0]);
-    if (area2 == 0.0 || !isfinite(area2)) return;           /* zero-area triangles contribute 0 */
+    if (area2 == 0.0 || !isfinite(area2)) return 0;         /* zero-area triangles contribute 0 */
     t->orient = area2 > 0 ? 1.0 : -1.0;                      /* inside test works for either orientation */
     for (int e = 0; e < 3; ++e) {
         int a = e, b = (e + 1) % 3;
@@ -346,7 +352,7 @@ static void pair_normalised(const okern *K, otri *t, double out[3]) {
     t->D = (t->y[1] - t->y[2]) * (t->x[0] - t->x[2]) + (t->x[2] - t->x[1]) * (t->y[0] - t->y[2]);
     double amax = 0.0;
     for (int i = 0; i < t->nn; ++i) amax = fmax(amax, fabs(t->A[i]));
-    octx c = {K, t, 12, 0, 4e-15 * fmax(1.0, (t->nn == 10 ? 3.0 : 1.0) * amax)};
+    octx c = {K, t, 12, 0, 4e-15 * fmax(1.0, (t->nn == 10 ? 3.0 : 1.0) * amax), 0};
     double br[1024];
     int nb = 0;
     br[nb++] = -OR_PI;
@@ -401,6 +407,7 @@ static void pair_normalised(const okern *K, otri *t, double out[3]) {
     for (int i = 0; i + 1 < nb; ++i) {
         if (br[i + 1] > br[i]) adapt(&c, br[i], br[i + 1], 0, out);
     }
+    return c.capped;
 }
 
 /* ------------------------------------------------------------------ */
@@ -409,7 +416,9 @@ static void pair_normalised(const okern *K, otri *t, double out[3]) {
 
 /* One (particle, triangle) pair in world coordinates.
  * tri6 = x0,y0,x1,y1,x2,y2 ; A = nodal values (nn of them).
- * out = (I, Gx, Gy) including C_d and the 1/h of the gradient. */
+ * out = (I, Gx, Gy) including C_d and the 1/h of the gradient.
+ * Returns 0, -1 for bad arguments, or 1 when the adaptive rule stopped at
+ * its depth or call cap (out is written but unverified). */
 int oracle_pair(int kernel_id, double h, int nn, double px, double py, const double *tri6,
                 const double *A, double *out) {
     okern K;
@@ -423,11 +432,11 @@ int oracle_pair(int kernel_id, double h, int nn, double px, double py, const dou
     }
     for (int i = 0; i < nn; ++i) t.A[i] = A[i];
     double o[3];
-    pair_normalised(&K, &t, o);
+    const int capped = pair_normalised(&K, &t, o);
     out[0] = K.Cd * o[0];
     out[1] = K.Cd * o[1] / h;
     out[2] = K.Cd * o[2] / h;
-    return 0;
+    return capped;
 }
 
 /* Same, with the triangle already in the support-normalised frame (h = 1). */
@@ -436,7 +445,10 @@ int oracle_pair_normalised(int kernel_id, int nn, const double *tri6, const doub
 }
 
 /* Per-particle sums over a CSR pair list (eq. boundaryint).
- * tri: [6][T] SoA, nodal: [nn][T], per_pair (nullable): [3][P]. */
+ * tri: [6][T] SoA, nodal: [nn][T], per_pair (nullable): [3][P].
+ * Returns 0; -1 for bad arguments; -2 if a triangle index is out of range;
+ * otherwise the number of pairs whose adaptive rule stopped at a cap
+ * (positive: all outputs are written, those pairs are unverified). */
 int oracle_integrate(int kernel_id, double h, int nn, int64_t N, const double *px, const double *py,
                      int64_t T, const double *tri, const double *nodal, const int64_t *offsets,
                      const int32_t *tri_idx, double *I, double *Gx, double *Gy, double *per_pair,
@@ -449,7 +461,8 @@ int oracle_integrate(int kernel_id, double h, int nn, int64_t N, const double *p
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
     int bad = 0;
-#pragma omp parallel for schedule(dynamic, 16) reduction(|:bad)
+    long capped = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(|:bad) reduction(+:capped)
     for (int64_t i = 0; i < N; ++i) {
         double si = 0, sx = 0, sy = 0;
         for (int64_t q = offsets[i]; q < offsets[i + 1]; ++q) {
@@ -463,14 +476,15 @@ int oracle_integrate(int kernel_id, double h, int nn, int64_t N, const double *p
             }
             for (int a = 0; a < nn; ++a) t.A[a] = nodal[a * T + j];
             double o[3];
-            pair_normalised(&K, &t, o);
+            capped += pair_normalised(&K, &t, o);
             double vi = K.Cd * o[0], vx = K.Cd * o[1] / h, vy = K.Cd * o[2] / h;
             if (per_pair) { per_pair[q] = vi; per_pair[P + q] = vx; per_pair[2 * P + q] = vy; }
             si += vi; sx += vx; sy += vy;
         }
         I[i] = si; Gx[i] = sx; Gy[i] = sy;
     }
-    return bad ? -2 : 0;
+    if (bad) return -2;
+    return capped > 0x7fffffff ? 0x7fffffff : (int)capped;
 }
 
 /* ------------------------------------------------------------------ */

@@ -118,7 +118,7 @@ def field_polynomial(V, A):
     return out
 
 
-def mp_pair_field(v, A, kid, dps=32):
+def mp_pair_field(v, A, kid, dps=32, check=None):
     """(I, Gx, Gy) of one pair with C_d, support 1, particle at the origin.
 
     v: three vertices; A: nodal values (1, 3 or 10).  Polar coordinates about
@@ -126,7 +126,10 @@ def mp_pair_field(v, A, kid, dps=32):
     each ray, integrated exactly; the angle by mpmath.quad between
     breakpoints (vertex directions, edge directions, feet of perpendiculars,
     circle crossings of every kernel piece, and a geometric grading towards
-    the directions of edge lines passing close to the particle)."""
+    the directions of edge lines passing close to the particle), by fixed
+    Gauss-Legendre rules of 24 and 48 points, bisecting an interval until the
+    two agree to `check` per unit angle (default 10^(8-dps)); raises if that
+    does not happen within 40 bisections."""
     import sympy as sp
     from tests.exact import c_d
     mp.mp.dps = dps
@@ -217,9 +220,49 @@ def mp_pair_field(v, A, kid, dps=32):
         wrapped.append(b)
     br = sorted(set(wrapped))
     cd = mp.mpf(sp.Rational(c_d(kid) * sp.pi).p) / sp.Rational(c_d(kid) * sp.pi).q / mp.pi
+    # fixed Gauss-Legendre rules of 24 and 48 points on every interval (the
+    # integrand is analytic inside each one); their difference bounds the
+    # error, checked against `check`
+    lo_rule, hi_rule = _gl_rule(4), _gl_rule(5)
+    tol = mp.mpf(check) if check is not None else mp.mpf(10) ** (-dps + 8)
+
+    def rule(rl, lo, hi):
+        h2, m = (hi - lo) / 2, (hi + lo) / 2
+        a = [mp.mpf(0)] * 3
+        for x, w in rl:
+            v = f(m + h2 * x)
+            for comp in range(3):
+                a[comp] += w * h2 * v[comp]
+        return a
+
+    def integrate(lo, hi, depth):
+        a, b = rule(lo_rule, lo, hi), rule(hi_rule, lo, hi)
+        d = max(abs(b[c] - a[c]) for c in range(3))
+        if d <= tol * (hi - lo) or depth >= 40:
+            if d > tol * (hi - lo):
+                raise ArithmeticError(f"mp reference not converged on [{lo}, {hi}]: {d}")
+            return b
+        mid = (lo + hi) / 2
+        l, r = integrate(lo, mid, depth + 1), integrate(mid, hi, depth + 1)
+        return [l[c] + r[c] for c in range(3)]
+
     out = [mp.mpf(0)] * 3
     for lo, hi in zip(br[:-1], br[1:]):
         if hi > lo:
+            v = integrate(lo, hi, 0)
             for comp in range(3):
-                out[comp] += mp.quad(lambda th: f(th)[comp], [lo, hi])
+                out[comp] += v[comp]
     return [cd * x for x in out]
+
+
+_GL_CACHE = {}
+
+
+def _gl_rule(degree):
+    """(node, weight) pairs on [-1, 1] of mpmath's Gauss-Legendre rule of
+    3 * 2^(degree-1) points at the working precision."""
+    key = (degree, mp.mp.prec)
+    if key not in _GL_CACHE:
+        gl = mp.calculus.quadrature.GaussLegendre(mp.mp)
+        _GL_CACHE[key] = gl.calc_nodes(degree, mp.mp.prec)
+    return _GL_CACHE[key]

@@ -85,9 +85,10 @@ def test_mixed_band_wall():
 
 
 @pytest.mark.parametrize("kid", [0, 1, 2, 3])
-def test_mixed_slivers(kid):
+@pytest.mark.parametrize("order", [0, 1, 3])
+def test_mixed_slivers(kid, order):
     """Particles within 1e-8..1e-2 h of edges and vertices of 0.5-degree slivers."""
-    wl = W.sliver_stress(seed=3, grid=16, kernel=kid, field_order=0)
+    wl = W.sliver_stress(seed=3, grid=16, kernel=kid, field_order=order)
     check_mixed(wl)
 
 
@@ -195,10 +196,12 @@ def test_mixed_full_size_against_fp64_path():
 
 
 @pytest.mark.parametrize("kid", [0, 1, 2, 3])
-def test_mixed_precision_stress_full_size(kid):
-    """262,144 particles near 16,384 slivers, per kernel: mixed vs the FP64
-    path on every particle, 1024 sampled particles vs the oracle."""
-    wl = W.sliver_stress(seed=3, kernel=kid, field_order=0)
+@pytest.mark.parametrize("order", [0, 3])
+def test_mixed_precision_stress_full_size(kid, order):
+    """262,144 particles near 16,384 slivers, per kernel, constant and cubic
+    fields: mixed vs the FP64 path on every particle, 1024 sampled particles
+    vs the oracle."""
+    wl = W.sliver_stress(seed=3, kernel=kid, field_order=order)
     say(f"mixed stress kid={kid}: N={wl.n_particles} T={wl.n_triangles}")
     off, idx = gpu_pairs(wl)
     a = run(wl.kernel, wl.h, wl.px, wl.py, wl.tri, wl.nodal, off, idx, sb.MIXED)

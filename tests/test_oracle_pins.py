@@ -351,3 +351,43 @@ def test_definition_matches_mpmath_near_edges(case):
     ref = np.array([float(cd * x) for x in r])
     out = oracle.pair(0, 1.0, 0.0, 0.0, np.array(v).reshape(6), [1.0])
     np.testing.assert_allclose(out, ref, rtol=0, atol=2e-15)
+
+
+def _sliver_pairs():
+    """Pairs of the precision-stress recipe in the support-normalised frame:
+    (kernel, field order, vertices, nodal values) for particles near an edge
+    or a vertex of 0.5-degree slivers; every kernel with a cubic field, two
+    with a linear one."""
+    from paper_2507_21686_amd import workloads as W
+    pick = [(0, 3, 0), (1, 3, 9), (2, 3, 16), (3, 3, 29), (2, 1, 9), (1, 1, 16)]   # q 0, 16: edge; 9, 29: vertex
+    out = []
+    for kid, order, q in pick:
+        wl = W.sliver_stress(seed=11, grid=2, field_order=order)
+        off, idx = oracle.pairlist(wl.px, wl.py, wl.tri, wl.h)
+        own = np.repeat(np.arange(wl.n_particles), np.diff(off))
+        i, t = own[q], idx[q]
+        v = np.empty(6)
+        v[0::2] = (wl.tri[0::2, t] - wl.px[i]) / wl.h
+        v[1::2] = (wl.tri[1::2, t] - wl.py[i]) / wl.h
+        out.append((kid, order, v, wl.nodal[:, t].copy()))
+    return out
+
+
+SLIVER_PAIRS = _sliver_pairs()
+
+
+@pytest.mark.parametrize("case", range(len(SLIVER_PAIRS)))
+def test_definition_matches_mpmath_slivers_linear_cubic(case):
+    """The definition oracle on linear and cubic fields over 0.5-degree
+    slivers, particles 1e-8..1e-2 h from an edge or vertex, against a
+    26-digit mpmath evaluation of the same integral (exact radial polynomial
+    integrals, angular Gauss-Legendre rules bisected to convergence): within
+    the oracle's stated 2.5e-14 of the field scale."""
+    from tests.mp_reference import mp_pair_field
+    kid, order, v, A = SLIVER_PAIRS[case]
+    ref = np.array([float(x) for x in mp_pair_field(list(zip(v[0::2], v[1::2])), A, kid, dps=26)])
+    got = oracle.pair(kid, 1.0, 0.0, 0.0, v, A)
+    amax = float(np.abs(A).max()) * (3.0 if order == 3 else 1.0)
+    sI, sG = amax, float(2 * exact.c_d(kid) * exact.int_k(kid)) * amax
+    assert abs(got[0] - ref[0]) <= 2.5e-14 * max(abs(ref[0]), sI)
+    assert max(abs(got[1] - ref[1]), abs(got[2] - ref[2])) <= 2.5e-14 * max(abs(ref[1]), abs(ref[2]), sG)
