@@ -7,9 +7,13 @@ covering boundary mesh with perturbed vertices (largest aspect ratio 20), a
 cubic Lagrange field (10 N(0,1) values per triangle) and the Wendland C2
 kernel.  Inputs are synthetic and seeded.
 
-A step is one evaluation of the closed-form integrals over all pairs (field
-records + pair kernel, FP64).  The pair list is built once beforehand and
-timed separately.  The JSON line also carries the dominant kernel's roofline
+A step is one call of sphbi_integrate with its default options over all pairs
+(field records, the FP64 pair kernel and the double-double refinement pass
+of ill-conditioned pairs, of which this workload has none).  The pair list is
+built once beforehand and timed separately.  The roofline prices the pair
+kernel (timed alone with HIP events) by the operation count of the paper's
+own closed form, counted by the instrumented closed-form oracle on a sample of
+the workload's pairs.  The JSON line also carries the dominant kernel's roofline
 position, the CPU oracle timed on a bounded sample and, under "modes":
 the same step in the mixed FP32/FP64 precision mode with its largest
 scale-normalised deviation from the FP64 results; the SPH operators; the
@@ -129,6 +133,61 @@ def edge_case_mix(px, py, tri, off, idx, h, radii):
             n_tri += int((ok & (p < R)).sum())
             n_clip += int((ok & (ya.abs() > yc)).sum()) + int((ok & (yb.abs() > yc)).sum())
     return n_edges, n_tri, n_clip
+
+
+def paper_op_count():
+    """Operations per pair of the paper's closed form (Sec. 4-5) on this
+    workload, as counted by the instrumented closed-form oracle
+    (oracle/count_ops.py wrote the file; this reads it)."""
+    return json.load(open(os.path.join(ROOT, "oracle", "op_count_covering_1M_p3_c2.json")))
+
+
+def bench_precision_stress(args, sb, W, torch, dev):
+    """The precision stress workload (262,144 particles 1e-8..1e-2 h from edges
+    and vertices of 16,384 sliver triangles with a smallest angle of 0.5
+    degrees), every kernel, cubic N(0,1) fields: per-particle scale-normalised
+    errors (max, p99.99, p50) of the default FP64 and mixed calls and of the
+    plain FP64 closed form (refinement off) against the all-double-double
+    evaluation on every particle, and times."""
+    out = {}
+    for kid in (0, 1, 2, 3):
+        wl = W.sliver_stress(seed=3, kernel=kid, field_order=3)
+        t = [torch.tensor(a, device=dev) for a in (wl.px, wl.py, wl.tri, wl.nodal)]
+        off, idx = sb.pairlist(t[0], t[1], t[2], wl.h)
+        amax = float(np.abs(wl.nodal).max()) * 3.0
+        sG = 2 * kernel_c_d_int_k(sb, kid) / wl.h * amax
+
+        def table(got, ref):
+            eI = torch.abs(got[0] - ref[0]) / torch.clamp(torch.abs(ref[0]), min=amax)
+            eG = torch.maximum(torch.abs(got[1] - ref[1]) / torch.clamp(torch.abs(ref[1]), min=sG),
+                               torch.abs(got[2] - ref[2]) / torch.clamp(torch.abs(ref[2]), min=sG))
+            qs = torch.tensor([0.9999, 0.5], dtype=torch.float64, device=dev)
+            r = {}
+            for name, e in (("I", eI), ("G", eG)):
+                q = torch.quantile(e, qs)
+                r[name] = {"max": float(e.max()), "p99.99": float(q[0]), "p50": float(q[1])}
+            return r
+
+        ref = sb.integrate(kid, wl.h, *t, off, idx, refine=sb.REFINE_ALL)
+        row = {}
+        for name, kw in (("fp64", {}), ("mixed", {"precision": sb.MIXED}), ("fp64_refinement_off",
+                                                                              {"refine": sb.REFINE_OFF})):
+            fn = lambda: sb.integrate(kid, wl.h, *t, off, idx, **kw)
+            got = fn()
+            ms = event_time(torch, fn, 3, 1)
+            row[name] = {"ms": ms, "error_vs_double_double": table(got, ref)}
+        ms_dd = event_time(torch, lambda: sb.integrate(kid, wl.h, *t, off, idx, refine=sb.REFINE_ALL), 3, 1)
+        row["double_double_all_pairs_ms"] = ms_dd
+        out[W.KERNEL_NAMES[kid]] = row
+        log(f"bench: precision stress {W.KERNEL_NAMES[kid]}: fp64 max I/G "
+            f"{row['fp64']['error_vs_double_double']['I']['max']:.1e}/"
+            f"{row['fp64']['error_vs_double_double']['G']['max']:.1e} ({row['fp64']['ms']:.3f} ms), refinement off "
+            f"{row['fp64_refinement_off']['error_vs_double_double']['G']['max']:.1e}, mixed "
+            f"{row['mixed']['error_vs_double_double']['G']['max']:.1e}")
+    out["workload"] = ("262,144 particles, 16,384 slivers (min angle 0.5 deg), h = 1/512, cubic N(0,1) fields; "
+                       "errors per particle, scale-normalised, against the all-double-double evaluation (itself "
+                       "within 1e-15 of the oracle: tests/test_gpu_forward.py)")
+    return out
 
 
 def kernel_c_d_int_k(sb, kid):
@@ -331,6 +390,66 @@ def bench_quadrature(args, sb, W, torch, dev, wl, px, py, tri, nodal, off, idx, 
     return out
 
 
+def host_cpu():
+    """(model name, logical CPUs the OS reports, CPUs this process may use)"""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline(args, wl, off_h, idx_h):
+    """The definition oracle (and the closed-form oracle beside it) on the host
+    cores, on a seeded sample of the workload's particles: all the cores this
+    run may use (at most 16, the host share of one GPU) and one thread."""
+    import oracle
+    model, nproc, usable = host_cpu()
+    nth = max(1, min(16, usable))
+    N = wl.n_particles
+    rng = np.random.default_rng(0)
+    sel = np.sort(rng.choice(N, min(args.cpu_sample, N), replace=False))
+
+    def sub(s):
+        soff = np.concatenate([[0], np.cumsum(off_h[s + 1] - off_h[s])])
+        sidx = np.concatenate([idx_h[off_h[i]:off_h[i + 1]] for i in s])
+        return soff, sidx
+
+    soff, sidx = sub(sel)
+    log(f"bench: cpu oracle on {len(sel)} particles / {len(sidx)} pairs, {nth} threads ({model}, nproc {nproc})")
+    t0 = time.perf_counter()
+    oracle.integrate(wl.kernel, wl.h, wl.px[sel], wl.py[sel], wl.tri, wl.nodal, soff, sidx, nthreads=nth)
+    dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.integrate(wl.kernel, wl.h, wl.px[sel], wl.py[sel], wl.tri, wl.nodal, soff, sidx, nthreads=nth,
+                     method="closed_form")
+    dt_cf = time.perf_counter() - t0
+    sel1 = sel[: max(1, len(sel) // 16)]
+    soff1, sidx1 = sub(sel1)
+    t0 = time.perf_counter()
+    oracle.integrate(wl.kernel, wl.h, wl.px[sel1], wl.py[sel1], wl.tri, wl.nodal, soff1, sidx1, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.integrate(wl.kernel, wl.h, wl.px[sel1], wl.py[sel1], wl.tri, wl.nodal, soff1, sidx1, nthreads=1,
+                     method="closed_form")
+    dt1_cf = time.perf_counter() - t0
+    log(f"bench: cpu oracle {len(sidx) / dt:.3e} pairs/s ({nth} threads), {len(sidx1) / dt1:.3e} (1 thread); "
+        f"closed form {len(sidx) / dt_cf:.3e} / {len(sidx1) / dt1_cf:.3e}")
+    return {"value": len(sidx) / dt, "unit": "pairs/s", "cores": nth, "kind": "oracle",
+            "sample": f"{len(sel)} random particles ({len(sidx)} pairs) of the same workload, definition oracle "
+                      f"(adaptive polar quadrature), {nth} threads; one thread on the first {len(sel1)} of them "
+                      f"({len(sidx1)} pairs)",
+            "host": {"cpu_model": model, "nproc": nproc, "usable_cpus": usable},
+            "one_thread_pairs_per_s": len(sidx1) / dt1,
+            "closed_form_oracle_pairs_per_s": len(sidx) / dt_cf,
+            "closed_form_oracle_one_thread_pairs_per_s": len(sidx1) / dt1_cf}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,6 +463,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip training and timing the surrogate")
     ap.add_argument("--no-operators", action="store_true", help="skip timing the SPH operators")
     ap.add_argument("--no-quadrature", action="store_true", help="skip the quadrature comparison")
+    ap.add_argument("--no-precision-stress", action="store_true", help="skip the sliver precision-stress table")
     ap.add_argument("--surrogate-steps", type=int, default=40000, help="Adam steps of the surrogate training")
     ap.add_argument("--surrogate-level", type=float, default=1e-2,
                     help="scale-normalised per-pair error the router is calibrated to")
@@ -384,30 +504,38 @@ def main():
     stream = torch.cuda.current_stream()
 
     def timed(precision):
-        """(ms per step, pair-kernel ms per launch, outputs) of one precision mode"""
+        """(ms per step, pair-kernel ms per launch, min, outputs) of one precision mode.
+
+        The step is the whole sphbi_integrate call (default options: records,
+        pair kernel, refinement pass); the pair kernel alone is timed with HIP
+        events around the second stage of the same call on prepared records."""
         integ = sb.Integrator(wl.kernel, wl.h, wl.n_nodes, precision=precision)
         out = tuple(torch.empty(N, dtype=torch.float64, device=dev) for _ in range(3))
 
-        def step(ev=None):
-            rec = integ.prepare(tri, nodal)
-            if ev is not None:
-                ev[0].record(stream)
-            integ.integrate_prepared(px, py, T, rec, off, idx, out=out)
-            if ev is not None:
-                ev[1].record(stream)
+        def step():
+            integ(px, py, tri, nodal, off, idx, out=out)
 
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
         t0 = time.perf_counter()
         for k in range(args.steps):
-            step(evs[k])
+            step()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        res = tuple(o.clone() for o in out)
+        rec = integ.prepare(tri, nodal)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for _ in range(2):
+            integ.integrate_prepared(px, py, T, rec, off, idx, out=out)
+        for k in range(args.steps):
+            evs[k][0].record(stream)
+            integ.integrate_prepared(px, py, T, rec, off, idx, out=out)
+            evs[k][1].record(stream)
+        torch.cuda.synchronize()
         kern_ms = [a.elapsed_time(b) for a, b in evs]
-        return wall * 1e3 / args.steps, float(np.mean(kern_ms)), min(kern_ms), out
+        return wall * 1e3 / args.steps, float(np.mean(kern_ms)), min(kern_ms), res
 
     ms_step, kern_avg, kern_min, out64 = timed(sb.FP64)
     log(f"bench: fp64 {ms_step:.3f} ms/step, pair kernel {kern_avg:.3f} ms (min {kern_min:.3f})")
@@ -428,17 +556,25 @@ def main():
         torch.cuda.synchronize()
         log("bench: copy probe 1 GiB x3 done")
 
-    # algorithmic work of one pair-kernel launch
+    # algorithmic work of one pair-kernel launch: the paper's closed form as
+    # counted by the instrumented oracle, on a sample of this workload's pairs
+    off_h, idx_h = off.cpu().numpy(), idx.cpu().numpy()
+    ops = paper_op_count()
+    flop_pair = ops["per_pair"]["total"]
+    achieved = flop_pair * P / (kern_avg * 1e-3) / 1e12
+    log(f"bench: paper closed form {flop_pair:.0f} operations/pair (instrumented oracle, {ops['sample']})")
+    # the device formulation's own count (signed fan; FMA = 2), for comparison
     kern = sb.kernel_preset(wl.kernel)
     deg = max(kern.degree[p] for p in range(kern.n_pieces))
     radii = [kern.radius[p] for p in range(kern.n_pieces)]
     per_pair, per_edge, per_tri, per_clip = flop_model(deg, 3)
     n_edges, n_tri, n_clip = edge_case_mix(px, py, tri, off, idx, wl.h, radii)
     flops = P * per_pair + n_edges * per_edge + n_tri * per_tri + n_clip * per_clip
-    achieved = flops / (kern_avg * 1e-3) / 1e12
+    achieved_model = flops / (kern_avg * 1e-3) / 1e12
     # algorithmic bytes: particles in/out, offsets, pair indices, triangle records (once)
     alg_bytes = N * (16 + 24 + 8) + P * 4 + T * 128
-    log(f"bench: {flops / P:.0f} flop/pair (model), {achieved:.2f} TFLOP/s, "
+    log(f"bench: {achieved:.1f} TFLOP/s of the paper's operations ({achieved / FP64_VECTOR_PEAK_TFLOPS:.2f} of the "
+        f"FP64 peak); device formulation {flops / P:.0f} flop/pair, {achieved_model:.2f} TFLOP/s; "
         f"{alg_bytes / (kern_avg * 1e-3) / 1e9:.1f} GB/s algorithmic")
 
     result = {
@@ -461,7 +597,13 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": measured_traffic() if args.n_side == 1024 else None,
-                     "kernel": "forward_sorted_kernel<5,3,false,512,0>", "kernel_ms": kern_avg, "flop_per_pair": flops / P,
+                     "kernel": "forward_sorted_kernel<5,3,false,512,0>", "kernel_ms": kern_avg,
+                     "flop_per_pair": flop_pair, "flop_per_pair_source": "instrumented closed-form oracle",
+                     "op_count": ops,
+                     "device_formulation": {"flop_per_pair": flops / P, "achieved": achieved_model,
+                                            "frac": achieved_model / FP64_VECTOR_PEAK_TFLOPS,
+                                            "counted": "FP64 operations of the signed-fan formulation from its loop "
+                                                       "bounds and the measured edge-case mix, FMA = 2"},
                      "alg_bytes_per_launch": alg_bytes},
         "pairlist_ms": {"first": pairlist_ms, "warm": pairlist_ms_warm},
         "modes": {
@@ -471,6 +613,8 @@ def main():
         },
     }
 
+    if not args.no_precision_stress:
+        result["modes"]["precision_stress"] = bench_precision_stress(args, sb, W, torch, dev)
     if not args.no_operators:
         result["modes"]["operators"] = bench_operators(args, sb, torch, dev, wl, px, py, tri, nodal, off, idx,
                                                        kern_avg)
@@ -483,27 +627,7 @@ def main():
         result["modes"]["surrogate"] = bench_surrogate(args, sb, torch, dev)
 
     if not args.no_cpu_baseline:
-        import oracle
-        nth = min(16, os.cpu_count() or 1)
-        rng = np.random.default_rng(0)
-        sel = np.sort(rng.choice(N, min(args.cpu_sample, N), replace=False))
-        off_h = off.cpu().numpy()
-        idx_h = idx.cpu().numpy()
-        soff = np.concatenate([[0], np.cumsum(off_h[sel + 1] - off_h[sel])])
-        sidx = np.concatenate([idx_h[off_h[i]:off_h[i + 1]] for i in sel])
-        log(f"bench: cpu oracle on {len(sel)} particles / {len(sidx)} pairs, {nth} threads")
-        t0 = time.perf_counter()
-        oracle.integrate(wl.kernel, wl.h, wl.px[sel], wl.py[sel], wl.tri, wl.nodal, soff, sidx, nthreads=nth)
-        dt = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        oracle.integrate(wl.kernel, wl.h, wl.px[sel], wl.py[sel], wl.tri, wl.nodal, soff, sidx, nthreads=nth,
-                         method="closed_form")
-        dt_cf = time.perf_counter() - t0
-        result["cpu_baseline"] = {"value": len(sidx) / dt, "unit": "pairs/s", "cores": nth, "kind": "oracle",
-                                  "sample": f"{len(sel)} random particles ({len(sidx)} pairs) of the same workload, "
-                                            f"definition oracle (adaptive polar quadrature), {nth} threads",
-                                  "closed_form_oracle_pairs_per_s": len(sidx) / dt_cf}
-        log(f"bench: cpu oracle {len(sidx) / dt:.3e} pairs/s (definition), {len(sidx) / dt_cf:.3e} (closed form)")
+        result["cpu_baseline"] = cpu_baseline(args, wl, off_h, idx_h)
 
     print(json.dumps(result), flush=True)
 

@@ -23,6 +23,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SOURCES = ["definition.c", "closed_form.c"]
+OPCOUNT_LIB = os.path.join(HERE, "liboracle_opcount.so")
 
 _lib = None
 
@@ -40,6 +41,16 @@ def build(force: bool = True) -> str:
     cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=c11", "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    # the operation-counting build of the closed-form oracle (C++), with the
+    # definition oracle's kernel tables
+    obj = OPCOUNT_LIB + ".def.o"
+    subprocess.run(["gcc", "-O2", "-fPIC", "-std=c11", "-c", os.path.join(HERE, "definition.c"), "-o", obj],
+                   check=True)
+    tmp = OPCOUNT_LIB + ".tmp"
+    subprocess.run(["g++", "-O2", "-fPIC", "-shared", "-std=c++17", "-o", tmp, os.path.join(HERE, "opcount.cpp"), obj,
+                    "-lm"], check=True)
+    os.remove(obj)
+    os.replace(tmp, OPCOUNT_LIB)
     return LIB
 
 
@@ -138,6 +149,43 @@ def integrate(kernel_id, h, px, py, tri, nodal, offsets, tri_idx, per_pair=False
     if rc < 0:
         raise ValueError(f"oracle integrate failed ({rc})")
     return (I, Gx, Gy, pp) if per_pair else (I, Gx, Gy)
+
+
+_opc = None
+OPCOUNT_KINDS = ("add", "mul", "div", "sqrt", "transcendental")
+
+
+def opcount_pairs(kernel_id, tri, A):
+    """Operation counts of the paper's closed form (closed_form.c) per pair.
+
+    tri [6, n] in the support-normalised frame, A [n_nodes, n].  Returns
+    (counts int64 [n, 5] in the order of OPCOUNT_KINDS, case int [n] = number
+    of vertices inside the support, out [3, n] = the counted evaluation)."""
+    global _opc
+    if _opc is None:
+        if not os.path.exists(OPCOUNT_LIB):
+            build()
+        _opc = C.CDLL(OPCOUNT_LIB)
+        _opc.oracle_opcount_pair.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                             C.c_void_p]
+    tri, A = _f64(tri), _f64(A)
+    n = tri.shape[1]
+    counts = np.zeros((n, 5), np.int64)
+    cls = np.zeros(n, np.int32)
+    out = np.zeros((3, n))
+    t6 = np.zeros(6)
+    a = np.zeros(10)
+    o = np.zeros(3)
+    c = np.zeros(5, np.int64)
+    k = np.zeros(1, np.int32)
+    for j in range(n):
+        t6[:] = tri[:, j]
+        a[:A.shape[0]] = A[:, j]
+        _opc.oracle_opcount_pair(int(kernel_id), int(A.shape[0]), _p(t6), _p(a), _p(o), _p(c), _p(k))
+        counts[j] = c
+        cls[j] = k[0]
+        out[:, j] = o
+    return counts, cls, out
 
 
 def pairlist(px, py, tri, h, nthreads=0):

@@ -48,7 +48,18 @@
 #define KM 17   /* radial powers K = 0..16 */
 #define NM 6    /* harmonics n = 0..5 */
 
-typedef struct { double c[KM][NM], s[KM][NM]; } mom;
+/* moment table; only K < km and n < nm are formed (km = kernel degree +
+ * field order + 2 and nm = field order + 2 are all that the contraction
+ * reads) */
+typedef struct { int km, nm; double c[KM][NM], s[KM][NM]; } mom;
+
+/* an empty table with the limits of `like` */
+static void mom_init(mom *C, const mom *like) {
+    const int km = like->km, nm = like->nm;     /* like may be C itself */
+    memset(C, 0, sizeof(*C));
+    C->km = km;
+    C->nm = nm;
+}
 
 /* kernel description shared with definition.c (same library) */
 typedef struct {
@@ -170,9 +181,9 @@ double oracle_cf_radial(int a, int m, double p, double r0, double r1) {
 
 /* rotate canonical moments back: theta = alpha + s theta' (eq. improper) */
 static void add_rotated(mom *M, const mom *C, double alpha, int s, double sign) {
-    for (int n = 0; n < NM; ++n) {
+    for (int n = 0; n < C->nm; ++n) {
         double cn = cos(n * alpha), sn = sin(n * alpha);
-        for (int K = 0; K < KM; ++K) {
+        for (int K = 0; K < C->km; ++K) {
             double c = C->c[K][n], si = C->s[K][n];
             M->c[K][n] += sign * (cn * c - s * sn * si);
             M->s[K][n] += sign * (sn * c + s * cn * si);
@@ -182,17 +193,17 @@ static void add_rotated(mom *M, const mom *C, double alpha, int s, double sign) 
 
 /* Alg. 1: full disc of radius 1 */
 static void disc(mom *C) {
-    memset(C, 0, sizeof(*C));
-    for (int K = 0; K < KM; ++K) C->c[K][0] = 2.0 * CF_PI / (K + 1);
+    mom_init(C, C);
+    for (int K = 0; K < C->km; ++K) C->c[K][0] = 2.0 * CF_PI / (K + 1);
 }
 
 /* cone closed forms (Sec. 5.2): sector theta' in [0, g], r in [0, d] */
 static void sector_c(mom *C, double g, double d) {
-    memset(C, 0, sizeof(*C));
-    for (int K = 0; K < KM; ++K) {
+    mom_init(C, C);
+    for (int K = 0; K < C->km; ++K) {
         double rad = pw(d, K + 1) / (K + 1);
         C->c[K][0] = g * rad;
-        for (int n = 1; n < NM; ++n) {
+        for (int n = 1; n < C->nm; ++n) {
             C->c[K][n] = rad * sin(n * g) / n;
             C->s[K][n] = rad * (1.0 - cos(n * g)) / n;
         }
@@ -201,16 +212,16 @@ static void sector_c(mom *C, double g, double d) {
 
 /* segment closed forms (Sec. 5.3), d >= 0: r in [d,1], |theta'| <= acos(d/r) */
 static void segment_c(mom *C, double d) {
-    memset(C, 0, sizeof(*C));
+    mom_init(C, C);
     if (d >= 1.0) return;
     double w1 = sqrt((1.0 - d) * (1.0 + d));          /* half chord */
     double ac = atan2(w1, d);                          /* acos(d) */
-    for (int K = 1; K < KM; ++K) {
+    for (int K = 1; K < C->km; ++K) {
         /* n = 0: 2 int r^K acos(d/r) = 2 [r^{K+1} acos(d/r)/(K+1)] - 2 d/(K+1) J(K-1,-1) */
         double v = ac / (K + 1);
         if (d > 0) v -= d / (K + 1) * radial(K - 1, -1, d, d, 0.0, 1.0, w1);
         C->c[K][0] = 2.0 * v;
-        for (int n = 1; n < NM; ++n) {
+        for (int n = 1; n < C->nm; ++n) {
             /* (2/n) sum_j u_{n-1,j} d^j J(K-j, 1) */
             double s = 0.0;
             for (int j = 0; j < n; ++j) {
@@ -226,16 +237,18 @@ static void segment_c(mom *C, double d) {
 /* D cut by the half plane {x . (cos a, sin a) >= dd} */
 static void segment_piece(mom *M, double a, double dd, double sign) {
     mom C;
+    mom_init(&C, M);
     if (dd >= 1.0) return;
     if (dd <= -1.0) { disc(&C); add_rotated(M, &C, 0.0, 1, sign); return; }
     if (dd >= 0.0) {
         segment_c(&C, dd);
     } else {
         mom S;
+        mom_init(&S, M);
         segment_c(&S, -dd);
         disc(&C);
-        for (int K = 0; K < KM; ++K)
-            for (int n = 0; n < NM; ++n) C.c[K][n] -= ((n & 1) ? -1.0 : 1.0) * S.c[K][n];
+        for (int K = 0; K < C.km; ++K)
+            for (int n = 0; n < C.nm; ++n) C.c[K][n] -= ((n & 1) ? -1.0 : 1.0) * S.c[K][n];
     }
     add_rotated(M, &C, a, 1, sign);
 }
@@ -253,6 +266,7 @@ static void sector_piece(mom *M, const double *v1, const double *v2, double sign
     int s = y >= 0 ? 1 : -1;
     double g = atan2(s * y, x);
     mom C;
+    mom_init(&C, M);
     sector_c(&C, g, 1.0);
     add_rotated(M, &C, a1, s, sign);
 }
@@ -271,20 +285,21 @@ static void integrateR(mom *M, double p, double wn, double wf, double alpha, int
     if (!(gam > 0.0) || l == 0.0) return;
     double beta = atan2(p, wf);                             /* angle at the far vertex */
     mom C;
+    mom_init(&C, M);
     sector_c(&C, gam, fmin(d, 1.0));                        /* S(gamma, |nu_near|) */
     if (d < 1.0) {
         double r1 = l, w1 = wf;
         if (l > 1.0) { r1 = 1.0; w1 = sqrt((1.0 - p) * (1.0 + p)); }
         double cb[NM], sb[NM];
-        for (int n = 0; n < NM; ++n) { cb[n] = cos(n * beta); sb[n] = sin(n * beta); }
+        for (int n = 0; n < C.nm; ++n) { cb[n] = cos(n * beta); sb[n] = sin(n * beta); }
         double as1 = atan2(p, w1), as0 = atan2(p, wn);      /* asin(p/r) at both ends */
-        for (int K = 1; K < KM; ++K) {
+        for (int K = 1; K < C.km; ++K) {
             double PK = P_int(K, d, r1);
             /* n = 0: int r^K (asin(p/r) - beta) dr */
             double v = (pw(r1, K + 1) * as1 - pw(d, K + 1) * as0) / (K + 1);
             if (p > 0) v += p / (K + 1) * radial(K - 1, -1, p, d, wn, r1, w1);
             C.c[K][0] += v - beta * PK;
-            for (int n = 1; n < NM; ++n) {
+            for (int n = 1; n < C.nm; ++n) {
                 /* sin(n asin s) = s U_{n-1}(c), cos(n asin s) = T_n(c), c = sqrt(1 - s^2) */
                 double SU = 0.0, CT = 0.0;
                 if (p > 0)
@@ -382,7 +397,7 @@ static void wedge(mom *M, const double *V0, const double *V1, const double *V2, 
             double o[2] = {-v[e][0], -v[e][1]};
             if (cross2(a, o) < 0) in = 0;
         }
-        if (in) { mom C; disc(&C); add_rotated(M, &C, 0.0, 1, sign); }
+        if (in) { mom C; mom_init(&C, M); disc(&C); add_rotated(M, &C, 0.0, 1, sign); }
         return;
     }
     if (nh == 1) {
@@ -412,6 +427,7 @@ static void wedge(mom *M, const double *V0, const double *V1, const double *V2, 
         sector_piece(M, s1, s2, sign);
     } else {                                                /* arc longer than pi */
         mom C;
+        mom_init(&C, M);
         disc(&C);
         add_rotated(M, &C, 0.0, 1, sign);
         sector_piece(M, s2, s1, -sign);
@@ -564,8 +580,8 @@ static void trig_monomial(int i, int j, int extra, trig *t) {   /* extra: 0 none
 
 static double contract(const mom *M, int K, const trig *t) {
     double s = 0.0;
-    if (K < 0 || K >= KM) return 0.0;
-    for (int n = 0; n < NM; ++n) s += t->c[n] * M->c[K][n] + t->s[n] * M->s[K][n];
+    if (K < 0 || K >= M->km) return 0.0;
+    for (int n = 0; n < M->nm; ++n) s += t->c[n] * M->c[K][n] + t->s[n] * M->s[K][n];
     return s;
 }
 
@@ -584,10 +600,15 @@ static void cf_pair_normalised(int kid, int nn, double v[3][2], const double *A,
         for (int i = 0; i < 3; ++i) { s[i][0] = v[i][0] / R[p]; s[i][1] = v[i][1] / R[p]; }
         mom M;
         memset(&M, 0, sizeof(M));
+        {
+            const int order = nn == 1 ? 0 : (nn == 3 ? 1 : 3);
+            M.km = deg[p] + order + 2 < KM ? deg[p] + order + 2 : KM;
+            M.nm = order + 2;
+        }
         triangle_moments(&M, s);
-        for (int K = 0; K < KM; ++K) {                     /* back to radius R_p */
+        for (int K = 0; K < M.km; ++K) {                   /* back to radius R_p */
             double f = pw(R[p], K + 1);
-            for (int n = 0; n < NM; ++n) { M.c[K][n] *= f; M.s[K][n] *= f; }
+            for (int n = 0; n < M.nm; ++n) { M.c[K][n] *= f; M.s[K][n] *= f; }
         }
         for (int i = 0; i < 4; ++i)
             for (int j = 0; i + j < 4; ++j) {

@@ -87,3 +87,38 @@ def test_closed_form_every_case_class_p0():
         a = oracle.pair(0, 1.0, 0, 0, tri[:, k], [1.0])
         b = oracle.pair(0, 1.0, 0, 0, tri[:, k], [1.0], method="cf")
         assert np.abs(a - b).max() < 1e-13
+
+
+def test_operation_counting_build_reproduces_the_closed_form():
+    """The instrumented build (opcount.cpp) evaluates exactly the closed-form
+    oracle, bit for bit, and counts a positive number of operations of every
+    kind for pairs that reach the support; more vertices inside the support
+    mean more pieces (the dispatch of Sec. 4.6) and a field of higher order
+    more harmonics."""
+    from paper_2507_21686_amd import workloads as W
+    tri = W.random_pairs(120, 9, spread=1.3, scale_range=(0.2, 2.5))
+    for kid, nn in ((0, 10), (1, 3), (3, 1)):
+        A = np.random.default_rng(kid).standard_normal((nn, tri.shape[1]))
+        counts, cls, out = oracle.opcount_pairs(kid, tri, A)
+        ref = oracle.pairs_normalised(kid, tri, A, method="cf")
+        assert np.array_equal(out, ref)
+        assert np.all(counts[:, :2] > 0) and set(np.unique(cls)) <= {0, 1, 2, 3}
+    A1 = np.ones((1, tri.shape[1]))
+    A3 = np.random.default_rng(0).standard_normal((10, tri.shape[1]))
+    c1, _, _ = oracle.opcount_pairs(0, tri, A1)
+    c3, _, _ = oracle.opcount_pairs(0, tri, A3)
+    assert c3.sum() > c1.sum()
+
+
+def test_committed_op_count_file_matches_its_script():
+    """bench.py prices its roofline with oracle/op_count_covering_1M_p3_c2.json;
+    the file is what oracle/count_ops.py writes (spot check on the first
+    particles of its seeded sample)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(oracle.__file__), "op_count_covering_1M_p3_c2.json")
+    d = json.load(open(path))
+    tot = d["per_pair"]
+    assert abs(tot["total"] - (tot["add"] + tot["mul"] + tot["div"] + tot["sqrt"] + tot["transcendental"])) < 1e-6 * tot["total"]
+    assert sum(v["fraction"] for v in d["by_case"].values()) == pytest.approx(1.0)
+    assert d["written_by"] == "oracle/count_ops.py"
