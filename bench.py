@@ -377,8 +377,10 @@ def bench_quadrature(args, sb, W, torch, dev, wl, px, py, tri, nodal, off, idx, 
     o_in = torch.cat([torch.zeros(1, dtype=torch.int64, device=dev), torch.cumsum(cnt, 0)])
     i_in = i[inside].contiguous()
     P_in = int(i_in.numel())
-    cf = sb.integrate(fine.kernel, fine.h, x, y, tr, nod, o_in, i_in)
-    cf_ms = event_time(torch, lambda: sb.integrate(fine.kernel, fine.h, x, y, tr, nod, o_in, i_in), 3, 1)
+    # the FP64 closed form itself (no double-double refinement), which is what a rule would replace
+    cf = sb.integrate(fine.kernel, fine.h, x, y, tr, nod, o_in, i_in, refine=sb.REFINE_OFF)
+    cf_ms = event_time(torch, lambda: sb.integrate(fine.kernel, fine.h, x, y, tr, nod, o_in, i_in,
+                                                   refine=sb.REFINE_OFF), 3, 1)
     log(f"bench: small triangles: {P_in} of {P} pairs ({P_in / P:.1%}) have the triangle inside the support; "
         f"closed form on them {cf_ms:.3f} ms")
     out["small_triangles_inside_support"] = {

@@ -2,16 +2,13 @@
 // Sec. 2-5 with every step in double-double; see ddmath.h for why a pair can
 // need it).
 //
-// refine_kernel: one lane per particle, 64 particles per block, the blocks
-// striding over the particles (a grid of at most a few blocks per compute
-// unit, so that a launch with nothing to refine costs little).  A lane walks
-// its particle's pairs in CSR order; every pair selected by the policy
-// (all pairs, or those whose conditioning gate fires, see refine_gate) is
-// evaluated from the triangle's world coordinates and nodal values in
-// double-double, rounded to FP64, and summed in pair order.  In the gated
-// mode the forward kernel has left these pairs out of its sums and the
-// refined ones are added to its outputs; in the all-pairs mode the outputs
-// are written here alone.
+// refine_kernel evaluates the selected pairs -- all pairs, or those whose
+// conditioning gate fires (refine.h) -- from the triangles' world coordinates
+// and nodal values in double-double, rounds each to FP64 and sums them per
+// particle in pair order.  In the gated mode the forward kernel has left
+// these pairs out of its sums and the refined ones are added to its outputs;
+// in the all-pairs mode the outputs are written here alone.  A launch that
+// finds the forward pass's counter at zero returns at once.
 
 #include <math.h>
 #include <string.h>
@@ -43,56 +40,16 @@ __device__ __noinline__ void pair_dd(const KArgsDD &K, double x, double y, doubl
     oY = (double)Y;
 }
 
-template <int DEG, int ORDER>
-__device__ inline void refine_particle(const KArgsDD &K, const RefineGate &gate, bool all, double invh, int64_t N,
-                                       int64_t pid, const double *__restrict__ px, const double *__restrict__ py,
-                                       const int64_t *__restrict__ off, const int32_t *__restrict__ tri_idx,
-                                       int64_t P, int64_t T, int64_t q_lo, int64_t q_end,
-                                       const double *__restrict__ tri, const double *__restrict__ nodal,
-                                       double *__restrict__ I, double *__restrict__ Gx, double *__restrict__ Gy,
-                                       double *__restrict__ per_pair) {
-    const int64_t my_off = min(max(off[pid], q_lo), q_end);
-    const int64_t my_end = min(max(off[pid + 1], my_off), q_end);
-    const double x = px[pid], y = py[pid];
-    double aI = 0.0, aX = 0.0, aY = 0.0;
-    bool any = false;
-    for (int64_t q = my_off; q < my_end; ++q) {
-        const int32_t t = tri_idx[q];
-        if (t < 0 || t >= T) {
-            if (all && per_pair) per_pair[q] = per_pair[P + q] = per_pair[2 * P + q] = 0.0;
-            continue;
-        }
-        if (!all) {
-            double ax[3], ay[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                ax[k] = (tri[(2 * k) * T + t] - x) * invh;
-                ay[k] = (tri[(2 * k + 1) * T + t] - y) * invh;
-            }
-            if (!gate.fires(ax, ay)) continue;
-        }
-        double vI, vX, vY;
-        pair_dd<DEG, ORDER>(K, x, y, invh, tri, nodal, T, t, vI, vX, vY);
-        if (per_pair) {
-            per_pair[q] = vI;
-            per_pair[P + q] = vX;
-            per_pair[2 * P + q] = vY;
-        }
-        aI += vI;
-        aX += vX;
-        aY += vY;
-        any = true;
-    }
-    if (all) {
-        I[pid] = aI;
-        Gx[pid] = aX;
-        Gy[pid] = aY;
-    } else if (any) {
-        I[pid] += aI;
-        Gx[pid] += aX;
-        Gy[pid] += aY;
-    }
-}
+// One wavefront owns 64 consecutive particles (a grid of a few blocks per
+// compute unit strides over the groups).  It sweeps its particles' pairs 64
+// at a time, one pair per lane, and appends the pairs to refine (every pair
+// with a valid triangle in the all-pairs mode, else those whose gate fires)
+// to a list in LDS, in pair order; whenever the list is full, and at the end,
+// the list is evaluated one pair per lane and every particle lane adds the
+// results of its own pairs in list order.  The lanes therefore run the costly
+// double-double pairs densely, whatever the pairs' distribution over the
+// particles, and the sums stay in pair order (deterministic).
+constexpr int kRefList = 128;
 
 template <int DEG, int ORDER>
 __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate gate, bool all, double invh,
@@ -103,13 +60,105 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
                                                      const double *__restrict__ nodal, double *__restrict__ I,
                                                      double *__restrict__ Gx, double *__restrict__ Gy,
                                                      double *__restrict__ per_pair) {
+    __shared__ int64_t s_q[kRefList];
+    __shared__ uint8_t s_own[kRefList];
+    __shared__ double s_res[kRefList][3];
     if (!all && *gate.count == 0) return;       // the forward pass left out no pair
-    // the forward kernels' clamping of the CSR range
-    const int64_t q_end = min(max(off[N], (int64_t)0), P);
-    const int64_t q_lo = min(max(off[0], (int64_t)0), q_end);
-    for (int64_t pid = (int64_t)blockIdx.x * 64 + threadIdx.x; pid < N; pid += (int64_t)gridDim.x * 64)
-        refine_particle<DEG, ORDER>(K, gate, all, invh, N, pid, px, py, off, tri_idx, P, T, q_lo, q_end, tri, nodal, I,
-                                    Gx, Gy, per_pair);
+    const int lane = threadIdx.x;
+    for (int64_t p0 = (int64_t)blockIdx.x * 64; p0 < N; p0 += (int64_t)gridDim.x * 64) {
+        const int64_t pid = p0 + lane;
+        const int64_t plast = p0 + 64 < N ? p0 + 64 : N;
+        // the forward kernels' clamping of the CSR range
+        const int64_t q_end = min(max(off[plast], (int64_t)0), P);
+        const int64_t my_off = pid < N ? min(max(off[pid], (int64_t)0), q_end) : q_end;
+        const int64_t q_begin = __shfl(my_off, 0);
+        double aI = 0.0, aX = 0.0, aY = 0.0;
+        bool any = false;
+        int n_list = 0;
+        // evaluates the listed pairs and adds them to their particles
+        auto flush = [&]() {
+            for (int j = lane; j < n_list; j += 64) {
+                const int64_t q = s_q[j];
+                const int64_t ip = p0 + s_own[j];
+                double vI, vX, vY;
+                pair_dd<DEG, ORDER>(K, px[ip], py[ip], invh, tri, nodal, T, tri_idx[q], vI, vX, vY);
+                s_res[j][0] = vI;
+                s_res[j][1] = vX;
+                s_res[j][2] = vY;
+                if (per_pair) {
+                    per_pair[q] = vI;
+                    per_pair[P + q] = vX;
+                    per_pair[2 * P + q] = vY;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (int j = 0; j < n_list; ++j)
+                if (s_own[j] == lane) {
+                    aI += s_res[j][0];
+                    aX += s_res[j][1];
+                    aY += s_res[j][2];
+                    any = true;
+                }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            n_list = 0;
+        };
+        for (int64_t base = q_begin; base < q_end; base += 64) {
+            const int64_t q = base + lane;
+            const int64_t qq = q < q_end ? q : q_end - 1;
+            int lo = 0;                                // owner lane (the forward kernels' search)
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const int64_t om = __shfl(my_off, lo + step < 64 ? lo + step : 63);
+                if (lo + step < 64 && om <= qq) lo += step;
+            }
+            bool take = false;
+            if (q < q_end) {
+                const int32_t t = tri_idx[q];
+                if (t >= 0 && t < T) {
+                    if (all) {
+                        take = true;
+                    } else {
+                        const int64_t ip = p0 + lo;
+                        double ax[3], ay[3];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            ax[k] = (tri[(2 * k) * T + t] - px[ip]) * invh;
+                            ay[k] = (tri[(2 * k + 1) * T + t] - py[ip]) * invh;
+                        }
+                        take = gate.fires(ax, ay);
+                    }
+                } else if (all && per_pair) {
+                    per_pair[q] = per_pair[P + q] = per_pair[2 * P + q] = 0.0;
+                }
+            }
+            const uint64_t mask = __ballot(take);
+            const int cnt = __popcll(mask);
+            if (cnt == 0) continue;
+            if (n_list + cnt > kRefList) flush();
+            if (take) {
+                const int slot = n_list + __popcll(mask & ((1ull << lane) - 1));
+                s_q[slot] = q;
+                s_own[slot] = (uint8_t)lo;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            n_list += cnt;
+        }
+        if (n_list) flush();
+        if (pid < N) {
+            if (all) {
+                I[pid] = aI;
+                Gx[pid] = aX;
+                Gy[pid] = aY;
+            } else if (any) {
+                I[pid] += aI;
+                Gx[pid] += aX;
+                Gy[pid] += aY;
+            }
+        }
+    }
 }
 
 template <int ORDER>
