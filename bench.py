@@ -224,14 +224,25 @@ def bench_adjoint(args, sb, W, torch, dev):
     g = [torch.randn(wl.n_particles, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(k))
          for k in range(3)]
     P = int(idx.numel())
-    ms_b = event_time(torch, lambda: sb.integrate_backward(wl.kernel, wl.h, *t, off, idx, *g), max(3, args.steps // 4),
-                      2)
-    ms_f = event_time(torch, lambda: sb.integrate(wl.kernel, wl.h, *t, off, idx), max(3, args.steps // 4), 2)
-    log(f"bench: adjoint {ms_b:.3f} ms ({P / (ms_b * 1e-3):.3e} pairs/s), forward {ms_f:.3f} ms on the same pairs")
+    n = max(3, args.steps // 4)
+    ms_b = event_time(torch, lambda: sb.integrate_backward(wl.kernel, wl.h, *t, off, idx, *g), n, 2)
+    ms_bm = event_time(torch, lambda: sb.integrate_backward(wl.kernel, wl.h, *t, off, idx, *g, precision=sb.MIXED),
+                       n, 2)
+    ms_f = event_time(torch, lambda: sb.integrate(wl.kernel, wl.h, *t, off, idx, refine=sb.REFINE_OFF), n, 2)
+    ms_fr = event_time(torch, lambda: sb.integrate(wl.kernel, wl.h, *t, off, idx), n, 2)
+    a = sb.integrate_backward(wl.kernel, wl.h, *t, off, idx, *g, precision=sb.MIXED)
+    b = sb.integrate_backward(wl.kernel, wl.h, *t, off, idx, *g)
+    dev_m = {name: float((x - y).abs().max() / y.abs().max()) for name, x, y in
+             zip(("dpx", "dpy", "dtri", "dnodal"), a, b)}
+    log(f"bench: adjoint {ms_b:.3f} ms ({P / (ms_b * 1e-3):.3e} pairs/s), mixed {ms_bm:.3f} ms; forward {ms_f:.3f} ms "
+        f"(FP64 closed form), {ms_fr:.3f} ms (default, with refinement); mixed vs FP64 {dev_m}")
     return {"value": P / (ms_b * 1e-3), "unit": "pairs/s", "ms_per_step": ms_b, "forward_ms": ms_f,
-            "backward_over_forward": ms_b / ms_f,
+            "forward_refined_ms": ms_fr, "backward_over_forward": ms_b / ms_f,
+            "mixed": {"ms": ms_bm, "pairs_per_s": P / (ms_bm * 1e-3), "speedup_vs_fp64": ms_b / ms_bm,
+                      "max_rel_deviation_vs_fp64": dev_m},
             "workload": f"{wl.n_particles} particles, {wl.n_triangles} triangles, {P} pairs, Wendland C4, P3, "
-                        f"gradients for positions, vertices and nodal values (FP64)"}
+                        f"gradients for positions, vertices and nodal values (FP64 and mixed); the forward time is "
+                        f"the FP64 closed form without double-double refinement"}
 
 
 def bench_operators(args, sb, torch, dev, wl, px, py, tri, nodal, off, idx, fwd_ms):

@@ -264,8 +264,13 @@ def integrate_noalloc(kernel, h, px, py, tri, nodal, offsets, tri_idx, out, per_
     return I, Gx, Gy
 
 
-def integrate_backward(kernel, h, px, py, tri, nodal, offsets, tri_idx, gI, gGx, gGy):
-    """Vector-Jacobian product of :func:`integrate`: (dpx, dpy, dtri [6,T], dnodal [n_nodes,T])."""
+def integrate_backward(kernel, h, px, py, tri, nodal, offsets, tri_idx, gI, gGx, gGy, precision=FP64,
+                       tau_edge=1e-4):
+    """Vector-Jacobian product of :func:`integrate`: (dpx, dpy, dtri [6,T], dnodal [n_nodes,T]).
+
+    precision: FP64, or MIXED (square roots, reciprocals and, for constant and
+    linear fields, the sector angles on the FP32 units; FP64 within tau_edge*h
+    of an edge line)."""
     k = kernel_preset(kernel) if isinstance(kernel, int) else kernel
     px, py, tri, nodal = _dev(px), _dev(py), _dev(tri), _dev(nodal)
     gI, gGx, gGy = _dev(gI), _dev(gGx), _dev(gGy)
@@ -277,7 +282,7 @@ def integrate_backward(kernel, h, px, py, tri, nodal, offsets, tri_idx, gI, gGx,
     dnod = torch.empty_like(nodal)
     need = int(lib().sphbi_integrate_backward_workspace(T, P, nn))
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=px.device)
-    o = opts(FP64)
+    o = opts(precision, tau_edge)
     _check(lib().sphbi_integrate_backward(C.byref(k), C.byref(o), float(h), nn, N, _ptr(px), _ptr(py), T, _ptr(tri),
                                           _ptr(nodal), _ptr(offsets), _ptr(tri_idx), P, _ptr(gI), _ptr(gGx),
                                           _ptr(gGy), _ptr(dpx), _ptr(dpy), _ptr(dtri), _ptr(dnod), _ptr(ws),
@@ -288,15 +293,16 @@ def integrate_backward(kernel, h, px, py, tri, nodal, offsets, tri_idx, gI, gGx,
 class BoundaryIntegral(torch.autograd.Function):
     """(I, Gx, Gy) = boundary integrals with gradients for px, py, tri and nodal.
 
-    forward(px, py, tri, nodal, offsets, tri_idx, kernel, h); the pair list is
-    treated as constant (it changes only where the kernel vanishes).
+    forward(px, py, tri, nodal, offsets, tri_idx, kernel, h, precision=FP64); the
+    pair list is treated as constant (it changes only where the kernel
+    vanishes).  The backward pass runs in the forward pass's precision mode.
     """
 
     @staticmethod
-    def forward(ctx, px, py, tri, nodal, offsets, tri_idx, kernel, h):
+    def forward(ctx, px, py, tri, nodal, offsets, tri_idx, kernel, h, precision=FP64):
         ctx.save_for_backward(px, py, tri, nodal, offsets, tri_idx)
-        ctx.kernel, ctx.h = kernel, h
-        return integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx)
+        ctx.kernel, ctx.h, ctx.precision = kernel, h, precision
+        return integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx, precision=precision)
 
     @staticmethod
     def backward(ctx, gI, gGx, gGy):
@@ -306,8 +312,8 @@ class BoundaryIntegral(torch.autograd.Function):
         gGx = z if gGx is None else gGx.contiguous()
         gGy = z if gGy is None else gGy.contiguous()
         dpx, dpy, dtri, dnod = integrate_backward(ctx.kernel, ctx.h, px, py, tri, nodal, offsets, tri_idx,
-                                                  gI, gGx, gGy)
-        return dpx, dpy, dtri, dnod, None, None, None, None
+                                                  gI, gGx, gGy, precision=ctx.precision)
+        return dpx, dpy, dtri, dnod, None, None, None, None, None
 
 
 def integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx, per_pair=False, precision=FP64, tau_edge=1e-4,

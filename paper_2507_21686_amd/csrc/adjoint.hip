@@ -96,7 +96,8 @@ size_t backward_workspace(int64_t T, int64_t P, int n_nodes) {
     return o;
 }
 
-int launch_backward(int order, int deg, const KArgs &K, double h, int64_t N, const double *px, const double *py,
+int launch_backward(int order, int deg, int precision, double tau, const KArgs &K, double h, int64_t N,
+                    const double *px, const double *py,
                     const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,
                     const double *nodal, const double *gI, const double *gX, const double *gY, double *dpx,
                     double *dpy, double *dtri, double *dnodal, void *ws, hipStream_t s) {
@@ -121,14 +122,23 @@ int launch_backward(int order, int deg, const KArgs &K, double h, int64_t N, con
     (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr,
                                              (const int32_t *)nullptr, (int32_t *)nullptr, (int)Pn);
     const double invh = 1.0 / h;
+    const bool mixed = precision == SPHBI_MIXED;
     if (N > 0) {
-        if (order == 0)
-            launch_adj_deg<0>(deg, K, invh, N, px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy, pair_grad, s);
-        else if (order == 1)
-            launch_adjoint_linear(deg, K, invh, N, px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy,
-                                  pair_grad, s);
+        if (order == 1)
+            launch_adjoint_linear(deg, mixed, K, tau, invh, N, px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx,
+                                  dpy, pair_grad, s);
+        else if (order == 0 && mixed)
+            launch_adj_deg<0, true>(deg, K, tau, invh, N, px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy,
+                                    pair_grad, s);
+        else if (order == 0)
+            launch_adj_deg<0, false>(deg, K, tau, invh, N, px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx,
+                                     dpy, pair_grad, s);
+        else if (mixed)
+            launch_adj_deg<3, true>(deg, K, tau, invh, N, px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy,
+                                    pair_grad, s);
         else
-            launch_adj_deg<3>(deg, K, invh, N, px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy, pair_grad, s);
+            launch_adj_deg<3, false>(deg, K, tau, invh, N, px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx,
+                                     dpy, pair_grad, s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("adjoint launch: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }

@@ -5,11 +5,16 @@
 
 namespace sphbi {
 
-void launch_adjoint_linear(int deg, const KArgs &K, double invh, int64_t N, const double *px, const double *py,
-                           const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,
-                           const double *nodal, const double *gI, const double *gX, const double *gY, double *dpx,
-                           double *dpy, double *pair_grad, hipStream_t s) {
-    launch_adj_deg<1>(deg, K, invh, N, px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy, pair_grad, s);
+void launch_adjoint_linear(int deg, bool mixed, const KArgs &K, double tau, double invh, int64_t N, const double *px,
+                           const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T,
+                           const double *tri, const double *nodal, const double *gI, const double *gX,
+                           const double *gY, double *dpx, double *dpy, double *pair_grad, hipStream_t s) {
+    if (mixed)
+        launch_adj_deg<1, true>(deg, K, tau, invh, N, px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy,
+                                pair_grad, s);
+    else
+        launch_adj_deg<1, false>(deg, K, tau, invh, N, px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy,
+                                 pair_grad, s);
 }
 
 }  // namespace sphbi

@@ -44,8 +44,8 @@
 namespace sphbi {
 namespace {
 
-template <int DEG, int ORDER>
-__global__ __launch_bounds__(64) void adjoint_kernel(const KArgs K, double invh, int64_t N,
+template <int DEG, int ORDER, bool MIXED>
+__global__ __launch_bounds__(64) void adjoint_kernel(const KArgs K, double tau, double invh, int64_t N,
                                                       const double *__restrict__ px, const double *__restrict__ py,
                                                       const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ tri_idx, int64_t P, int64_t T,
@@ -107,7 +107,10 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const KArgs K, double invh,
                     // moments of the monomials about the particle and the
                     // boundary part of the vertex gradients, in one pass
                     double mom[NM], gv[6];
-                    pair_dual<DEG, ORDER>(K, ax, ay, area2, invh, cI, cX, cY, c, mom, gv);
+                    if (MIXED)
+                        pair_dual<DEG, ORDER, 3, MixedMath>(K, ax, ay, area2, invh, cI, cX, cY, c, mom, gv,
+                                                            MixedMath{false, ORDER >= 2}, tau);
+                    else pair_dual<DEG, ORDER>(K, ax, ay, area2, invh, cI, cX, cY, c, mom, gv);
 #pragma unroll
                     for (int k = 0; k < 6; ++k) grad[k] = gv[k];
                     // nodal values: the moments carried back through the
@@ -189,15 +192,15 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const KArgs K, double invh,
     }
 }
 
-template <int ORDER>
-void launch_adj_deg(int deg, const KArgs &K, double invh, int64_t N, const double *px, const double *py,
+template <int ORDER, bool MIXED>
+void launch_adj_deg(int deg, const KArgs &K, double tau, double invh, int64_t N, const double *px, const double *py,
                     const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,
                     const double *nodal, const double *gI, const double *gX, const double *gY, double *dpx,
                     double *dpy, double *pair_grad, hipStream_t s) {
     const unsigned blocks = (unsigned)((N + 63) / 64);
-#define SPHBI_ADJ(DG)                                                                                            \
-    hipLaunchKernelGGL((adjoint_kernel<DG, ORDER>), dim3(blocks), dim3(64), 0, s, K, invh, N, px, py, off,    \
-                       tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy, pair_grad)
+#define SPHBI_ADJ(DG)                                                                                              \
+    hipLaunchKernelGGL((adjoint_kernel<DG, ORDER, MIXED>), dim3(blocks), dim3(64), 0, s, K, tau, invh, N, px, py, \
+                       off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy, pair_grad)
     if (deg <= 3) SPHBI_ADJ(3);
     else if (deg <= 5) SPHBI_ADJ(5);
     else if (deg <= 8) SPHBI_ADJ(8);

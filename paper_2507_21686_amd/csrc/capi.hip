@@ -677,7 +677,6 @@ int sphbi_integrate_backward(const sphbi_kernel *kernel, const sphbi_opts *opts,
     sphbi_opts o;
     int rc = check_common(kernel, opts, &o, h, n_nodes, N, T, n_pairs);
     if (rc) return rc;
-    if (o.precision != SPHBI_FP64) { set_error("the adjoint runs in FP64 only"); return SPHBI_EUNSUPPORTED; }
     if (n_pairs > INT32_MAX) { set_error("more than 2^31-1 pairs"); return SPHBI_EUNSUPPORTED; }
     if (N > 0 && (!px || !py || !offsets || !gI || !gGx || !gGy || !dpx || !dpy)) {
         set_error("particle arrays are NULL");
@@ -693,8 +692,8 @@ int sphbi_integrate_backward(const sphbi_kernel *kernel, const sphbi_opts *opts,
     int deg = 0;
     const KArgs K = make_kargs(kernel, &deg);
     const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
-    return launch_backward(order, deg, K, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, gI, gGx, gGy, dpx,
-                           dpy, dtri, dnodal, ws, (hipStream_t)stream);
+    return launch_backward(order, deg, o.precision, o.tau_edge, K, h, N, px, py, offsets, tri_idx, n_pairs, T, tri,
+                           nodal, gI, gGx, gGy, dpx, dpy, dtri, dnodal, ws, (hipStream_t)stream);
 }
 
 size_t sphbi_operator_workspace(int64_t N, int64_t T) { return operator_workspace(N, T); }

@@ -75,7 +75,8 @@ int launch_forward(int order, int deg, int precision, double tau_edge, const KAr
                    hipStream_t s);
 
 size_t backward_workspace(int64_t T, int64_t P, int n_nodes);
-int launch_backward(int order, int deg, const KArgs &K, double h, int64_t N, const double *px, const double *py,
+int launch_backward(int order, int deg, int precision, double tau, const KArgs &K, double h, int64_t N,
+                    const double *px, const double *py,
                     const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,
                     const double *nodal, const double *gI, const double *gX, const double *gY, double *dpx,
                     double *dpy, double *dtri, double *dnodal, void *ws, hipStream_t s);
@@ -97,9 +98,9 @@ int launch_quadrature(int order, int deg, int n_gauss, const KArgs &K, double h,
                       const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T,
                       const double *tri, const double *nodal, double *I, double *Gx, double *Gy, hipStream_t s);
 // the adjoint pair kernel for linear fields (its own translation unit)
-void launch_adjoint_linear(int deg, const KArgs &K, double invh, int64_t N, const double *px, const double *py,
-                           const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T, const double *tri,
-                           const double *nodal, const double *gI, const double *gX, const double *gY, double *dpx,
-                           double *dpy, double *pair_grad, hipStream_t s);
+void launch_adjoint_linear(int deg, bool mixed, const KArgs &K, double tau, double invh, int64_t N, const double *px,
+                           const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P, int64_t T,
+                           const double *tri, const double *nodal, const double *gI, const double *gX,
+                           const double *gY, double *dpx, double *dpy, double *pair_grad, hipStream_t s);
 
 }  // namespace sphbi

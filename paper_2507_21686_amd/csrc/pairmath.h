@@ -1047,11 +1047,14 @@ __device__ inline void vertex_ray_dual(const KArgs &K, double vx, double vy, dou
 // term (LineSums): gv[2k], gv[2k+1] receive the line part of the gradient with
 // respect to vertex k (world units), for the field c about the particle
 // (units of h, record order).
-template <int DEG, int ORDER, int EDGE_UNROLL = 3>
+//
+// M is the precision policy of the square roots, reciprocals and angles
+// (ExactMath, or MixedMath with its FP64 islands within tau of an edge line).
+template <int DEG, int ORDER, int EDGE_UNROLL = 3, typename M = ExactMath>
 __device__ inline void pair_dual(const KArgs &K, const double *ax, const double *ay, double area2, double invh,
-                                 double cI, double cX, double cY, const double *c, double *mom, double *gv) {
+                                 double cI, double cX, double cY, const double *c, double *mom, double *gv,
+                                 const M &math = M(), double tau = 0.0) {
     using S = double;
-    const ExactMath math;
 #pragma unroll
     for (int k = 0; k < 6; ++k) gv[k] = 0.0;
     // adds the line integrals of edge e (vertex e to e+1) times the outward normal
@@ -1096,7 +1099,8 @@ __device__ inline void pair_dual(const KArgs &K, const double *ax, const double 
                 ls.ln.clear();
 #pragma unroll
                 for (int pc = 0; pc < 2; ++pc)
-                    if (pc < K.npieces) edge_piece<DEG, ORDER, S>(K, math, pc, S(0.0), la, lb, ra2, rb2, ls);
+                    if (pc < K.npieces) edge_piece<DEG, ORDER, S>(K, math.for_edge(0.0, tau), pc, S(0.0), la, lb, ra2,
+                                                                  rb2, ls);
                 S Ja, Jb;
                 ls.ln.finish(S(0.0), la, lb, ty, -tx, c, cI, cX, cY, invh, K.cd, Ja, Jb);
                 add_line(e, Ja, Jb, so * ty, -so * tx);
@@ -1111,9 +1115,10 @@ __device__ inline void pair_dual(const KArgs &K, const double *ax, const double 
             for (int n = 0; n < 5; ++n) sk.vb[m].c[n] = sk.vb[m].s[n] = sk.gb[m].c[n] = sk.gb[m].s[n] = 0.0;
         // pieces unrolled (at most two): a constant piece index keeps every
         // coefficient a scalar load from the argument block
+        const auto em = math.for_edge(p, tau);
 #pragma unroll
         for (int pc = 0; pc < 2; ++pc)
-            if (pc < K.npieces) edge_piece<DEG, ORDER, S>(K, math, pc, p, ya, yb, ra2, rb2, sk);
+            if (pc < K.npieces) edge_piece<DEG, ORDER, S>(K, em, pc, p, ya, yb, ra2, rb2, sk);
         // the edge's share of cI I + cX GX + cY GY in the edge frame:
         // cI eI - (1/h) (gn eX + gt eY), (gn, gt) = cotangent in (n, t)
         const S wX = -invh * (cX * nx + cY * ny), wY = -invh * (cY * nx - cX * ny);

@@ -361,3 +361,81 @@ def test_pairs_outside_the_csr_range_contribute_nothing():
                                              torch.zeros(1, dtype=torch.int64, device=DEV), idx, z, z, z)
     torch.cuda.synchronize()
     assert torch.all(dtri == 0) and torch.all(dnod == 0)
+
+
+def test_mixed_adjoint_against_fp64_gradient():
+    """The adjoint in the mixed precision mode (square roots, reciprocals and,
+    for constant and linear fields, sector angles on the FP32 units) on the
+    differentiation workload (262,144 particles, Wendland C4, cubic field):
+    every particle, triangle and nodal gradient against the FP64 adjoint (to
+    1e-6 of the gradient scale), and 4,096 sampled pairs against the oracle's
+    FP64 gradient (4th-order central differences of the definition oracle,
+    themselves within 1e-9 of the exact gradient), also to 1e-6."""
+    wl = W.covering_workload(n_side=512, nx=64, ny=128, seed=4, kernel=1, field_order=3)
+    say("mixed adjoint, full size")
+    t, off, idx, g, tg = setup(wl)
+    a = sb.integrate_backward(wl.kernel, wl.h, *t, off, idx, *tg, precision=sb.MIXED)
+    b = sb.integrate_backward(wl.kernel, wl.h, *t, off, idx, *tg)
+    torch.cuda.synchronize()
+    sG = metrics.grad_scale(wl.kernel, wl.h)
+    amax = 3.0 * float(np.abs(wl.nodal).max())
+    gmax = float(np.abs(g).max())
+    # scales: d(I, G)/dx ~ (S_G, S_G/h), d(I, G)/dA ~ (1, S_G) per unit field, summed over a triangle's pairs
+    S_pos = amax * sG * gmax * (1 + 2 / wl.h)
+    for k, (x, y) in enumerate(zip(a, b)):
+        x, y = x.cpu().numpy(), y.cpu().numpy()
+        scale = S_pos * (6.0 if k == 2 else 1.0) if k < 3 else gmax * (1 + 2 * sG) * 6.0
+        err = np.abs(x - y).max() / scale
+        say(f"  output {k}: max |mixed - fp64| / scale = {err:.2e}")
+        assert err <= 1e-6
+    # 4,096 sampled pairs, each on its own particle and triangle copy
+    off_h, idx_h = off.cpu().numpy(), idx.cpu().numpy()
+    rng = np.random.default_rng(12)
+    sel = np.sort(rng.choice(len(idx_h), 4096, replace=False))
+    own = owners(off_h)
+    ip, it = own[sel], idx_h[sel].astype(np.int64)
+    M = len(sel)
+    px, py = wl.px[ip].copy(), wl.py[ip].copy()
+    tri = np.ascontiguousarray(wl.tri[:, it])
+    nod = np.ascontiguousarray(wl.nodal[:, it])
+    off1 = np.arange(M + 1, dtype=np.int64)
+    idx1 = np.arange(M, dtype=np.int32)
+    gg = rng.standard_normal((3, M))
+    tt = [torch.as_tensor(x, device=DEV) for x in (px, py, tri, nod)]
+    dpx, dpy, dtri, dnod = sb.integrate_backward(wl.kernel, wl.h, *tt, torch.as_tensor(off1, device=DEV),
+                                                 torch.as_tensor(idx1, device=DEV),
+                                                 *[torch.as_tensor(x, device=DEV) for x in gg], precision=sb.MIXED)
+    torch.cuda.synchronize()
+    got = np.concatenate([dpx.cpu().numpy()[None], dpy.cpu().numpy()[None], dtri.cpu().numpy()])
+
+    def loss(px_, py_, tri_, nod_=nod):
+        I, Gx, Gy = oracle.integrate(wl.kernel, wl.h, px_, py_, tri_, nod_, off1, idx1, nthreads=NTH)
+        return gg[0] * I + gg[1] * Gx + gg[2] * Gy
+
+    e = 1e-3 * wl.h
+    ref = np.zeros((8, M))
+    for c in range(8):
+        vals = {}
+        for s_ in (-2, -1, 1, 2):
+            px_, py_, tri_ = px.copy(), py.copy(), tri.copy()
+            if c == 0:
+                px_ += s_ * e
+            elif c == 1:
+                py_ += s_ * e
+            else:
+                tri_[c - 2] += s_ * e
+            vals[s_] = loss(px_, py_, tri_)
+        ref[c] = (8 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12 * e)
+    S = 3.0 * np.abs(nod).max(0) * sG * (np.abs(gg[0]) + (np.abs(gg[1]) + np.abs(gg[2])) / wl.h)
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), S)
+    say(f"  4096 pairs vs oracle gradient: worst scaled err {err.max():.2e}, median {np.median(err):.2e}")
+    assert err.max() <= 1e-6
+    dn = dnod.cpu().numpy()
+    refn = np.zeros_like(dn)
+    for n in range(wl.n_nodes):
+        unit = np.zeros_like(nod)
+        unit[n] = 1.0
+        refn[n] = loss(px, py, tri, unit)
+    errn = np.abs(dn - refn).max() / np.abs(refn).max()
+    say(f"  nodal vs oracle: scaled err {errn:.2e}")
+    assert errn <= 1e-6
