@@ -106,6 +106,11 @@ typedef struct {
     double tau_edge;    /* MIXED: pairs whose particle lies within tau_edge*h of an
                            edge line or vertex are evaluated in FP64 (default 1e-4) */
     double refine_gate; /* threshold on Kf kappa^order; 0 = the precision's default */
+    uint8_t *pair_status; /* optional DEVICE array [n_pairs] (sphbi_integrate, _noalloc,
+                             _prepared): per pair 1 if any of its three results is not
+                             finite (NaN or Inf from degenerate or non-finite input), else 0;
+                             pairs outside [offsets[0], offsets[N]) are left as they were.
+                             NULL (the default) writes nothing. */
 } sphbi_opts;
 
 /* Fills *out with a preset kernel: Wendland C2 (1-q)^4(1+4q), C4

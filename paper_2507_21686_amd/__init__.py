@@ -40,7 +40,7 @@ class SphbiKernel(C.Structure):
 
 class SphbiOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("refine", C.c_int32), ("tau_edge", C.c_double),
-                ("refine_gate", C.c_double)]
+                ("refine_gate", C.c_double), ("pair_status", C.c_void_p)]
 
 
 class SphbiGrid(C.Structure):
@@ -216,7 +216,9 @@ class Integrator:
                "sphbi_integrate_prepared")
         return (I, Gx, Gy, pp) if per_pair else (I, Gx, Gy)
 
-    def __call__(self, px, py, tri, nodal, offsets, tri_idx, per_pair: bool = False, out=None):
+    def __call__(self, px, py, tri, nodal, offsets, tri_idx, per_pair: bool = False, out=None, status=None):
+        """sphbi_integrate; status: optional uint8 device tensor [P] receiving
+        the per-pair non-finite flags."""
         px, py, tri, nodal = _dev(px), _dev(py), _dev(tri), _dev(nodal)
         offsets, tri_idx = _dev(offsets, torch.int64), _dev(tri_idx, torch.int32)
         N, T, P = px.numel(), tri.shape[1], tri_idx.numel()
@@ -230,7 +232,13 @@ class Integrator:
             I, Gx, Gy = out
         pp = torch.empty((3, P), dtype=torch.float64, device=px.device) if per_pair else None
         ws = self.workspace(T, px.device)
-        _check(lib().sphbi_integrate(C.byref(self.kernel), C.byref(self.opts), self.h, self.n_nodes, N, _ptr(px),
+        o = SphbiOpts.from_buffer_copy(self.opts)
+        if status is not None:
+            status = _dev(status, torch.uint8)
+            if status.numel() < P:
+                raise SphbiError("status must have one entry per pair")
+            o.pair_status = _ptr(status)
+        _check(lib().sphbi_integrate(C.byref(self.kernel), C.byref(o), self.h, self.n_nodes, N, _ptr(px),
                                      _ptr(py), T, _ptr(tri), _ptr(nodal), _ptr(offsets), _ptr(tri_idx), P, _ptr(I),
                                      _ptr(Gx), _ptr(Gy), _ptr(pp), _ptr(ws), ws.numel(), _stream()),
                "sphbi_integrate")
@@ -317,10 +325,11 @@ class BoundaryIntegral(torch.autograd.Function):
 
 
 def integrate(kernel, h, px, py, tri, nodal, offsets, tri_idx, per_pair=False, precision=FP64, tau_edge=1e-4,
-              refine=REFINE_AUTO, refine_gate=0.0):
-    """Per-particle (I, Gx, Gy) [N] (and optionally per-pair [3, P]) on the GPU."""
+              refine=REFINE_AUTO, refine_gate=0.0, status=None):
+    """Per-particle (I, Gx, Gy) [N] (and optionally per-pair [3, P]) on the GPU;
+    status: optional uint8 tensor [P] for the per-pair non-finite flags."""
     return Integrator(kernel, h, nodal.shape[0], precision, tau_edge, refine, refine_gate)(
-        px, py, tri, nodal, offsets, tri_idx, per_pair=per_pair)
+        px, py, tri, nodal, offsets, tri_idx, per_pair=per_pair, status=status)
 
 
 # ----------------------------------------------------------------------------

@@ -538,7 +538,7 @@ int sphbi_integrate_prepared(const sphbi_kernel *kernel, const sphbi_opts *opts,
     const KArgs K = make_kargs(kernel, &deg);
     const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
     return launch_forward(order, deg, o.precision, o.tau_edge, K, refine_off(), h, N, px, py, offsets, tri_idx,
-                          n_pairs, T, rec, I, Gx, Gy, per_pair, (hipStream_t)stream);
+                          n_pairs, T, rec, I, Gx, Gy, per_pair, (hipStream_t)stream, o.pair_status);
 }
 
 }  // extern "C"
@@ -592,7 +592,7 @@ int integrate_run(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, 
     hipStream_t s = (hipStream_t)stream;
     if (o.refine == SPHBI_REFINE_ALL)
         return launch_refine(order, deg, K, refine_off(), true, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, I,
-                             Gx, Gy, per_pair, s);
+                             Gx, Gy, per_pair, s, o.pair_status);
     // the refinement counter sits behind the records
     unsigned long long *count = (unsigned long long *)((char *)rec + records_bytes(T));
     RefineGate gate = T > 0 ? make_gate(o, order, K) : refine_off();
@@ -600,10 +600,10 @@ int integrate_run(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, 
     int rc = field_prepare(h, n_nodes, T, tri, nodal, rec, rec_bytes, stream, gate.order ? count : nullptr);
     if (rc) return rc;
     rc = launch_forward(order, deg, o.precision, o.tau_edge, K, gate, h, N, px, py, offsets, tri_idx, n_pairs, T, rec,
-                        I, Gx, Gy, per_pair, s);
+                        I, Gx, Gy, per_pair, s, o.pair_status);
     if (rc || !gate.order) return rc;
     return launch_refine(order, deg, K, gate, false, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, I, Gx, Gy,
-                         per_pair, s);
+                         per_pair, s, o.pair_status);
 }
 
 int check_integrate_args(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,

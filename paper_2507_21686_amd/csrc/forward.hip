@@ -56,10 +56,10 @@ int launch_prepare(int order, int64_t T, const double *tri, const double *nodal,
 int launch_forward(int order, int deg, int precision, double tau_edge, const KArgs &K, const RefineGate &gate,
                    double h, int64_t N, const double *px, const double *py, const int64_t *offsets,
                    const int32_t *tri_idx, int64_t P, int64_t T, const double *rec, double *I, double *Gx, double *Gy,
-                   double *per_pair, hipStream_t s) {
+                   double *per_pair, hipStream_t s, uint8_t *status) {
     if (N == 0) return SPHBI_OK;
     const FwdArgs a{tau_edge, 1.0 / h, N, px, py, offsets, tri_idx, rec, I, Gx, Gy, per_pair, P, T, nullptr, nullptr,
-                    gate};
+                    gate, status};
     if (precision == SPHBI_MIXED) launch_fwd_order<true>(order, deg, K, a, s);
     else launch_fwd_order<false>(order, deg, K, a, s);
     hipError_t e = hipGetLastError();

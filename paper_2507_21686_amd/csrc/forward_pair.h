@@ -142,7 +142,8 @@ __global__ __launch_bounds__(64, fwd_waves(DEG, ORDER, MIXED)) void forward_kern
                                                       double *__restrict__ Gx, double *__restrict__ Gy,
                                                       double *__restrict__ per_pair, int64_t P, int64_t T,
                                                       const double *__restrict__ rec2,
-                                                      const double *__restrict__ gam, const RefineGate gate) {
+                                                      const double *__restrict__ gam, const RefineGate gate,
+                                                      uint8_t *__restrict__ status) {
     const int lane = threadIdx.x & 63;
     const int64_t p0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
     if (p0 >= N) return;                               // whole wavefront
@@ -203,6 +204,7 @@ __global__ __launch_bounds__(64, fwd_waves(DEG, ORDER, MIXED)) void forward_kern
                 per_pair[P + q] = vX;
                 per_pair[2 * P + q] = vY;
             }
+            if (status) status[q] = !(isfinite(vI) && isfinite(vX) && isfinite(vY));
         }
         // segmented inclusive scan over lanes (segments = owners, contiguous)
 #pragma unroll
@@ -253,7 +255,8 @@ __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_wav
     const KArgs K, double tau, double invh, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
     const int64_t *__restrict__ off, const int32_t *__restrict__ tri_idx, const double *__restrict__ rec,
     double *__restrict__ I, double *__restrict__ Gx, double *__restrict__ Gy, double *__restrict__ per_pair, int64_t P,
-    int64_t T, const double *__restrict__ rec2, const double *__restrict__ gam, const RefineGate gate) {
+    int64_t T, const double *__restrict__ rec2, const double *__restrict__ gam, const RefineGate gate,
+    uint8_t *__restrict__ status) {
     __shared__ double s_res[SW][3];
     __shared__ uint16_t s_perm[SW];
     __shared__ uint8_t s_own[SW];
@@ -387,6 +390,7 @@ __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_wav
                     per_pair[P + q] = vX;
                     per_pair[2 * P + q] = vY;
                 }
+                if (status) status[q] = !(isfinite(vI) && isfinite(vX) && isfinite(vY));
                 s_res[item][0] = vI;
                 s_res[item][1] = vX;
                 s_res[item][2] = vY;
@@ -431,6 +435,7 @@ struct FwdArgs {
     int64_t P, T;
     const double *rec2, *gam;      // combined fields only
     RefineGate gate;               // plain fields: pairs left to the refinement pass
+    uint8_t *status;               // nullable: per pair, 1 when an output is not finite
 };
 
 // Both kernels run one wavefront (64 particles) per block.
@@ -441,11 +446,11 @@ void launch_fwd_t(const KArgs &K, const FwdArgs &a, hipStream_t s) {
     if constexpr (fwd_sorted(DEG, ORDER) || FM == kFieldDivCurl || FM == kFieldPairWeight)
         hipLaunchKernelGGL((forward_sorted_kernel<DEG, ORDER, MIXED, SW, FM>), dim3((unsigned)waves), dim3(64), 0,
                            s, K, a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair,
-                           a.P, a.T, a.rec2, a.gam, a.gate);
+                           a.P, a.T, a.rec2, a.gam, a.gate, a.status);
     else
         hipLaunchKernelGGL((forward_kernel<DEG, ORDER, MIXED, FM>), dim3((unsigned)waves), dim3(64), 0, s, K,
                            a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair, a.P,
-                           a.T, a.rec2, a.gam, a.gate);
+                           a.T, a.rec2, a.gam, a.gate, a.status);
 }
 
 template <int ORDER, bool MIXED, int FM = kFieldPlain>

@@ -72,7 +72,7 @@ int launch_forward(int order, int deg, int precision, double tau_edge, const KAr
                    double h, int64_t N,
                    const double *px, const double *py, const int64_t *offsets, const int32_t *tri_idx,
                    int64_t P, int64_t T, const double *rec, double *I, double *Gx, double *Gy, double *per_pair,
-                   hipStream_t s);
+                   hipStream_t s, uint8_t *status = nullptr);
 
 size_t backward_workspace(int64_t T, int64_t P, int n_nodes);
 int launch_backward(int order, int deg, int precision, double tau, const KArgs &K, double h, int64_t N,

@@ -62,6 +62,6 @@ KArgsDD make_kargs_dd(const KArgs &K);
 int launch_refine(int order, int deg, const KArgs &K, const RefineGate &gate, bool all, double h, int64_t N,
                   const double *px, const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P,
                   int64_t T, const double *tri, const double *nodal, double *I, double *Gx, double *Gy,
-                  double *per_pair, hipStream_t s);
+                  double *per_pair, hipStream_t s, uint8_t *status = nullptr);
 
 }  // namespace sphbi

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
                                                      const double *__restrict__ tri,
                                                      const double *__restrict__ nodal, double *__restrict__ I,
                                                      double *__restrict__ Gx, double *__restrict__ Gy,
-                                                     double *__restrict__ per_pair) {
+                                                     double *__restrict__ per_pair, uint8_t *__restrict__ status) {
     __shared__ int64_t s_q[kRefList];
     __shared__ uint8_t s_own[kRefList];
     __shared__ double s_res[kRefList][3];
@@ -90,6 +90,7 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
                     per_pair[P + q] = vX;
                     per_pair[2 * P + q] = vY;
                 }
+                if (status) status[q] = !(isfinite(vI) && isfinite(vX) && isfinite(vY));
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -129,8 +130,9 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
                         }
                         take = gate.fires(ax, ay);
                     }
-                } else if (all && per_pair) {
-                    per_pair[q] = per_pair[P + q] = per_pair[2 * P + q] = 0.0;
+                } else if (all) {
+                    if (per_pair) per_pair[q] = per_pair[P + q] = per_pair[2 * P + q] = 0.0;
+                    if (status) status[q] = 0;
                 }
             }
             const uint64_t mask = __ballot(take);
@@ -165,7 +167,7 @@ template <int ORDER>
 void launch_refine_order(int deg, const KArgsDD &K, const RefineGate &g, bool all, double invh, int64_t N,
                          const double *px, const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P,
                          int64_t T, const double *tri, const double *nodal, double *I, double *Gx, double *Gy,
-                         double *per_pair, hipStream_t s) {
+                         double *per_pair, hipStream_t s, uint8_t *status) {
     // a few waves per compute unit: enough to fill the chip when every pair
     // is refined (the kernel runs one wave per SIMD), little to launch when
     // none is
@@ -176,7 +178,7 @@ void launch_refine_order(int deg, const KArgsDD &K, const RefineGate &g, bool al
     const unsigned blocks = (unsigned)(want < cap ? want : cap);
 #define SPHBI_REF(DG)                                                                                          \
     hipLaunchKernelGGL((refine_kernel<DG, ORDER>), dim3(blocks), dim3(64), 0, s, K, g, all, invh, N, px, py, off, \
-                       tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair)
+                       tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, status)
     if (deg <= 3) SPHBI_REF(3);
     else if (deg <= 5) SPHBI_REF(5);
     else if (deg <= 8) SPHBI_REF(8);
@@ -220,16 +222,18 @@ KArgsDD make_kargs_dd(const KArgs &K) {
 int launch_refine(int order, int deg, const KArgs &K, const RefineGate &gate, bool all, double h, int64_t N,
                   const double *px, const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P,
                   int64_t T, const double *tri, const double *nodal, double *I, double *Gx, double *Gy,
-                  double *per_pair, hipStream_t s) {
+                  double *per_pair, hipStream_t s, uint8_t *status) {
     if (N == 0) return SPHBI_OK;
     const KArgsDD D = make_kargs_dd(K);
     const double invh = 1.0 / h;
     if (order == 0)
-        launch_refine_order<0>(deg, D, gate, all, invh, N, px, py, off, tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, s);
+        launch_refine_order<0>(deg, D, gate, all, invh, N, px, py, off, tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, s, status);
     else if (order == 1)
-        launch_refine_order<1>(deg, D, gate, all, invh, N, px, py, off, tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, s);
+        launch_refine_order<1>(deg, D, gate, all, invh, N, px, py, off, tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, s,
+                               status);
     else
-        launch_refine_order<3>(deg, D, gate, all, invh, N, px, py, off, tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, s);
+        launch_refine_order<3>(deg, D, gate, all, invh, N, px, py, off, tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, s,
+                               status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("refine launch: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
     return SPHBI_OK;

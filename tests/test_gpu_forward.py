@@ -417,3 +417,31 @@ def test_refine_modes():
         run_gpu(*args, refine=7)
     with pytest.raises(sb.SphbiError, match="refine_gate"):
         run_gpu(*args, refine_gate=-1.0)
+
+
+def test_pair_status_flags_non_finite_pairs():
+    """The per-pair status (sphbi_opts.pair_status): 1 exactly for the pairs
+    whose results are not finite (a triangle with a NaN nodal value, one with
+    an infinite vertex), 0 for the others, in every refinement mode."""
+    say("pair status")
+    wl = W.covering_workload(n_side=64, nx=8, ny=16, seed=2, kernel=1, field_order=3)
+    nod = wl.nodal.copy()
+    tri = wl.tri.copy()
+    nod[4, 10] = np.nan
+    tri[2, 20] = np.inf
+    tpx, tpy, ttri, tnod = to_dev(wl.px, wl.py, tri, nod)
+    off, idx = sb.pairlist(*to_dev(wl.px, wl.py, wl.tri), wl.h)      # pairs of the finite mesh
+    torch.cuda.synchronize()
+    bad = np.isin(idx.cpu().numpy(), [10, 20])
+    assert bad.any()
+    for refine in (sb.REFINE_AUTO, sb.REFINE_OFF, sb.REFINE_ALL):
+        st = torch.full((idx.numel(),), 7, dtype=torch.uint8, device=DEV)
+        _, _, _, pp = sb.integrate(wl.kernel, wl.h, tpx, tpy, ttri, tnod, off, idx, per_pair=True, refine=refine,
+                                   status=st)
+        torch.cuda.synchronize()
+        s = st.cpu().numpy()
+        fin = np.all(np.isfinite(pp.cpu().numpy()), axis=0)
+        assert set(np.unique(s)) <= {0, 1}
+        assert np.array_equal(s.astype(bool), ~fin)
+        assert s[np.isin(idx.cpu().numpy(), [10])].all()       # NaN field values propagate
+        assert not s[~bad].any()
