@@ -38,14 +38,16 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "pairmath.h"
 
 namespace sphbi {
 namespace {
 
-template <int DEG, int ORDER, bool MIXED>
-__global__ __launch_bounds__(64) void adjoint_kernel(const KArgs K, double tau, double invh, int64_t N,
+template <int DEG, int ORDER, bool MIXED, typename KA>
+__global__ __launch_bounds__(64) void adjoint_kernel(const KA K, double tau, double invh, int64_t N,
                                                       const double *__restrict__ px, const double *__restrict__ py,
                                                       const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ tri_idx, int64_t P, int64_t T,
@@ -108,9 +110,9 @@ __global__ __launch_bounds__(64) void adjoint_kernel(const KArgs K, double tau, 
                     // boundary part of the vertex gradients, in one pass
                     double mom[NM], gv[6];
                     if (MIXED)
-                        pair_dual<DEG, ORDER, 3, MixedMath>(K, ax, ay, area2, invh, cI, cX, cY, c, mom, gv,
+                        pair_dual<DEG, ORDER, 3, MixedMath, KA>(K, ax, ay, area2, invh, cI, cX, cY, c, mom, gv,
                                                             MixedMath{false, ORDER >= 2}, tau);
-                    else pair_dual<DEG, ORDER>(K, ax, ay, area2, invh, cI, cX, cY, c, mom, gv);
+                    else pair_dual<DEG, ORDER, 3, ExactMath, KA>(K, ax, ay, area2, invh, cI, cX, cY, c, mom, gv);
 #pragma unroll
                     for (int k = 0; k < 6; ++k) grad[k] = gv[k];
                     // nodal values: the moments carried back through the
@@ -198,9 +200,12 @@ void launch_adj_deg(int deg, const KArgs &K, double tau, double invh, int64_t N,
                     const double *nodal, const double *gI, const double *gX, const double *gY, double *dpx,
                     double *dpy, double *pair_grad, hipStream_t s) {
     const unsigned blocks = (unsigned)((N + 63) / 64);
-#define SPHBI_ADJ(DG)                                                                                              \
-    hipLaunchKernelGGL((adjoint_kernel<DG, ORDER, MIXED>), dim3(blocks), dim3(64), 0, s, K, tau, invh, N, px, py, \
-                       off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy, pair_grad)
+#define SPHBI_ADJ(DG)                                                                                         \
+    with_zero_pattern<DG>(K, [&](const auto &KZ) {                                                           \
+        using KA = std::decay_t<decltype(KZ)>;                                                              \
+        hipLaunchKernelGGL((adjoint_kernel<DG, ORDER, MIXED, KA>), dim3(blocks), dim3(64), 0, s, KZ, tau, invh, N, \
+                           px, py, off, tri_idx, P, T, tri, nodal, gI, gX, gY, dpx, dpy, pair_grad);            \
+    })
     if (deg <= 3) SPHBI_ADJ(3);
     else if (deg <= 5) SPHBI_ADJ(5);
     else if (deg <= 8) SPHBI_ADJ(8);

@@ -61,6 +61,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "pairmath.h"
 #include "refine.h"
@@ -103,8 +105,8 @@ __host__ __device__ constexpr int fwd_edge_unroll(int deg, int order) { return o
 // harmonics then spill about 120 B per lane, and that still runs a quarter
 // faster than one wave without spills (0.77 vs 1.04 ms on the covering mesh).
 __host__ __device__ constexpr int dc_waves(int) { return 2; }
-template <int DEG, int ORDER>
-__device__ inline void pair_div_curl_rot(const KArgs &K, double x, double y, double invh, const double *__restrict__ r,
+template <int DEG, int ORDER, typename KA>
+__device__ inline void pair_div_curl_rot(const KA &K, double x, double y, double invh, const double *__restrict__ r,
                                          const double *__restrict__ r2, int rot, double &div, double &curl) {
     div = curl = 0.0;
     double ax[3], ay[3];
@@ -132,8 +134,8 @@ __device__ inline void pair_div_curl_rot(const KArgs &K, double x, double y, dou
     curl = oX[1] - oY[0];
 }
 
-template <int DEG, int ORDER, bool MIXED, int FM>
-__global__ __launch_bounds__(64, fwd_waves(DEG, ORDER, MIXED)) void forward_kernel(const KArgs K, double tau, double invh, int64_t N,
+template <int DEG, int ORDER, bool MIXED, int FM, typename KA>
+__global__ __launch_bounds__(64, fwd_waves(DEG, ORDER, MIXED)) void forward_kernel(const KA K, double tau, double invh, int64_t N,
                                                       const double *__restrict__ px,
                                                       const double *__restrict__ py,
                                                       const int64_t *__restrict__ off,
@@ -250,9 +252,9 @@ __global__ __launch_bounds__(64, fwd_waves(DEG, ORDER, MIXED)) void forward_kern
 // four per block the block's LDS and slots stay held until its slowest wave
 // ends.  With one, every finished wave frees its slot at once (10-15% faster
 // on the covering mesh, same results bit for bit).
-template <int DEG, int ORDER, bool MIXED, int SW, int FM>
+template <int DEG, int ORDER, bool MIXED, int SW, int FM, typename KA>
 __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_waves(DEG, ORDER, MIXED)) void forward_sorted_kernel(
-    const KArgs K, double tau, double invh, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
+    const KA K, double tau, double invh, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
     const int64_t *__restrict__ off, const int32_t *__restrict__ tri_idx, const double *__restrict__ rec,
     double *__restrict__ I, double *__restrict__ Gx, double *__restrict__ Gy, double *__restrict__ per_pair, int64_t P,
     int64_t T, const double *__restrict__ rec2, const double *__restrict__ gam, const RefineGate gate,
@@ -438,19 +440,24 @@ struct FwdArgs {
     uint8_t *status;               // nullable: per pair, 1 when an output is not finite
 };
 
-// Both kernels run one wavefront (64 particles) per block.
+// Both kernels run one wavefront (64 particles) per block.  A kernel with
+// the Wendland zero pattern of its degree bound runs the instantiation that
+// leaves those terms out.
 template <int DEG, int ORDER, bool MIXED, int FM>
 void launch_fwd_t(const KArgs &K, const FwdArgs &a, hipStream_t s) {
     const int64_t waves = (a.N + 63) / 64;
     constexpr int SW = ORDER >= 2 ? 512 : 256;     // LDS: 14 or 7 KB per one-wave block
-    if constexpr (fwd_sorted(DEG, ORDER) || FM == kFieldDivCurl || FM == kFieldPairWeight)
-        hipLaunchKernelGGL((forward_sorted_kernel<DEG, ORDER, MIXED, SW, FM>), dim3((unsigned)waves), dim3(64), 0,
-                           s, K, a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair,
-                           a.P, a.T, a.rec2, a.gam, a.gate, a.status);
-    else
-        hipLaunchKernelGGL((forward_kernel<DEG, ORDER, MIXED, FM>), dim3((unsigned)waves), dim3(64), 0, s, K,
-                           a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair, a.P,
-                           a.T, a.rec2, a.gam, a.gate, a.status);
+    with_zero_pattern<DEG>(K, [&](const auto &KZ) {
+        using KA = std::decay_t<decltype(KZ)>;
+        if constexpr (fwd_sorted(DEG, ORDER) || FM == kFieldDivCurl || FM == kFieldPairWeight)
+            hipLaunchKernelGGL((forward_sorted_kernel<DEG, ORDER, MIXED, SW, FM, KA>), dim3((unsigned)waves),
+                               dim3(64), 0, s, KZ, a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx,
+                               a.Gy, a.per_pair, a.P, a.T, a.rec2, a.gam, a.gate, a.status);
+        else
+            hipLaunchKernelGGL((forward_kernel<DEG, ORDER, MIXED, FM, KA>), dim3((unsigned)waves), dim3(64), 0, s,
+                               KZ, a.tau, a.invh, a.N, a.px, a.py, a.off, a.tri_idx, a.rec, a.I, a.Gx, a.Gy, a.per_pair,
+                               a.P, a.T, a.rec2, a.gam, a.gate, a.status);
+    });
 }
 
 template <int ORDER, bool MIXED, int FM = kFieldPlain>

@@ -32,6 +32,52 @@ struct KArgs {
     double cd;
 };
 
+// KArgs whose monomial coefficients b_k are known at compile time to vanish
+// in every piece for each bit k of ZM (same layout; the launches pass it in
+// place of KArgs).  The Wendland kernels have b_1 = b_3 = ... = 0 below
+// their degree (their profile is even to that order), and the instantiations
+// for them leave those terms out of the kernel contraction.
+template <unsigned ZM>
+struct KArgsZ : KArgs {};
+template <typename KA>
+struct CoefZeros {
+    static constexpr unsigned mask = 0;
+};
+template <unsigned ZM>
+struct CoefZeros<KArgsZ<ZM>> {
+    static constexpr unsigned mask = ZM;
+};
+// The zero pattern the instantiations for a degree bound are built for: odd
+// k up to the bound's Wendland kernel (C2: b_1; C4: b_1, b_3; C6: b_1, b_3, b_5).
+__host__ __device__ constexpr unsigned wendland_zeros(int deg) {
+    return deg == 5 ? 0x2u : deg == 8 ? 0xAu : deg == 11 ? 0x2Au : 0u;
+}
+// Bits k with b_k = 0 in every piece of K.
+inline unsigned kernel_zero_mask(const KArgs &K) {
+    unsigned m = 0;
+    for (int k = 0; k <= kMaxDeg; ++k) {
+        bool z = true;
+        for (int p = 0; p < K.npieces; ++p) z = z && K.b[p][k] == 0.0;
+        if (z) m |= 1u << k;
+    }
+    return m;
+}
+// Calls f(KArgsZ<wendland_zeros(DEG)>) when K has that zero pattern, else
+// f(K) (the generic instantiation).
+template <int DEG, typename F>
+inline void with_zero_pattern(const KArgs &K, F &&f) {
+    constexpr unsigned wz = wendland_zeros(DEG);
+    if constexpr (wz != 0) {
+        if ((kernel_zero_mask(K) & wz) == wz) {
+            KArgsZ<wz> kz;
+            static_cast<KArgs &>(kz) = K;
+            f(kz);
+            return;
+        }
+    }
+    f(K);
+}
+
 // Per-triangle record written by the field preparation kernel: vertices
 // (world units) and the field as a polynomial about vertex 0 in units of h,
 // A(v0 + h eta) = sum e_ij eta_x^i eta_y^j, ordered e00 e10 e01 e20 e11 e02

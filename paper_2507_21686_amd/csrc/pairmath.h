@@ -423,9 +423,11 @@ struct LineSums {
         for (int i = 0; i < NK1; ++i) K1[i] = 0.0;
     }
     // the radial terms of piece pc, from ya to yb (either direction)
-    __device__ void add(const KArgs &K, int pc, const S *H, const S *P) {
+    template <typename KA>
+    __device__ void add(const KA &K, int pc, const S *H, const S *P) {
 #pragma unroll
         for (int j = 0; j <= DEG; ++j) {
+            if (CoefZeros<KA>::mask >> j & 1u) continue;
             const double bj = K.b[pc][j];
 #pragma unroll
             for (int i = 0; i < NG0; ++i) G0[i] = fma(bj, H[2 * i + j + 1], G0[i]);
@@ -530,7 +532,8 @@ template <int DEG, int ORDER, typename S>
 struct BasisLineSink : BasisSink<ORDER, S> {
     static constexpr int kHMax = LineSums<DEG, ORDER, S>::kHMax, kPMax = LineSums<DEG, ORDER, S>::kPMax;
     LineSums<DEG, ORDER, S> ln;
-    __device__ void radial(const KArgs &K, int pc, S, const S *H, const S *P) { ln.add(K, pc, H, P); }
+    template <typename KA>
+    __device__ void radial(const KA &K, int pc, S, const S *H, const S *P) { ln.add(K, pc, H, P); }
 };
 
 // The line sums alone, for an edge on a line through the particle: it has no
@@ -540,7 +543,8 @@ struct LineSink {
     static constexpr int kHMax = LineSums<DEG, ORDER, S>::kHMax, kPMax = LineSums<DEG, ORDER, S>::kPMax;
     static constexpr bool kOnLine = true;
     LineSums<DEG, ORDER, S> ln;
-    __device__ void radial(const KArgs &K, int pc, S, const S *H, const S *P) { ln.add(K, pc, H, P); }
+    template <typename KA>
+    __device__ void radial(const KA &K, int pc, S, const S *H, const S *P) { ln.add(K, pc, H, P); }
     template <typename C>
     __device__ void sector(int, C, C, const S *, const S *) {}
     __device__ void begin(int) {}
@@ -557,6 +561,7 @@ __host__ __device__ inline void edge_piece(const KA &K, const M &math, int pc, S
                                            Sink &sink) {
     constexpr int HMAX = DEG + ORDER + 1 > Sink::kHMax ? DEG + ORDER + 1 : Sink::kHMax;
     constexpr int PMAX = DEG + ORDER > Sink::kPMax ? DEG + ORDER : Sink::kPMax;
+    constexpr unsigned kZ = CoefZeros<KA>::mask;       // b_k known to vanish
     const double R = K.R[pc];
     const S yc = p < R ? S(math.sqrt_((R - p) * (R + p))) : S(0.0);
     const S aya = fabs(ya), ayb = fabs(yb);
@@ -646,28 +651,32 @@ __host__ __device__ inline void edge_piece(const KA &K, const M &math, int pc, S
         for (int j = 0; j <= m; ++j) {
             S s = 0.0;
 #pragma unroll
-            for (int k = 0; k <= DEG; ++k) s = fma(coef_bq(K, pc, m, k), H[k + 1 + m - j], s);
+            for (int k = 0; k <= DEG; ++k)
+                if (!(kZ >> k & 1u)) s = fma(coef_bq(K, pc, m, k), H[k + 1 + m - j], s);
             Ac[j] = s;
         }
 #pragma unroll
         for (int j = 0; j < m; ++j) {
             S s = 0.0;
 #pragma unroll
-            for (int k = 0; k <= DEG; ++k) s = fma(coef_bq(K, pc, m, k), P[k + m - j], s);
+            for (int k = 0; k <= DEG; ++k)
+                if (!(kZ >> k & 1u)) s = fma(coef_bq(K, pc, m, k), P[k + m - j], s);
             As[j] = s;
         }
 #pragma unroll
         for (int j = 0; j <= m + 1; ++j) {
             S s = 0.0;
 #pragma unroll
-            for (int k = 1; k <= DEG; ++k) s = fma(coef_kbq(K, pc, m, k), H[k + m - j], s);
+            for (int k = 1; k <= DEG; ++k)
+                if (!(kZ >> k & 1u)) s = fma(coef_kbq(K, pc, m, k), H[k + m - j], s);
             Bc[j] = s;
         }
 #pragma unroll
         for (int j = 0; j <= m; ++j) {
             S s = 0.0;
 #pragma unroll
-            for (int k = 1; k <= DEG; ++k) s = fma(coef_kbq(K, pc, m, k), P[k + m - 1 - j], s);
+            for (int k = 1; k <= DEG; ++k)
+                if (!(kZ >> k & 1u)) s = fma(coef_kbq(K, pc, m, k), P[k + m - 1 - j], s);
             Bs[j] = s;
         }
         // value harmonics n = m, m-2, ...
@@ -1050,8 +1059,8 @@ __device__ inline void vertex_ray_dual(const KArgs &K, double vx, double vy, dou
 //
 // M is the precision policy of the square roots, reciprocals and angles
 // (ExactMath, or MixedMath with its FP64 islands within tau of an edge line).
-template <int DEG, int ORDER, int EDGE_UNROLL = 3, typename M = ExactMath>
-__device__ inline void pair_dual(const KArgs &K, const double *ax, const double *ay, double area2, double invh,
+template <int DEG, int ORDER, int EDGE_UNROLL = 3, typename M = ExactMath, typename KA = KArgs>
+__device__ inline void pair_dual(const KA &K, const double *ax, const double *ay, double area2, double invh,
                                  double cI, double cX, double cY, const double *c, double *mom, double *gv,
                                  const M &math = M(), double tau = 0.0) {
     using S = double;

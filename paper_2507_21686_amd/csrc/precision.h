@@ -48,14 +48,27 @@ __device__ inline double rsqrt_nr(double x) {
     r = fma(0.5 * r, e, r);
     return tiny ? r * 0x1p256 : r;
 }
+// The same for arguments that are lengths: x is raised to the smallest
+// normal number first (one instruction in place of the scaling), which
+// changes nothing for normal x; a subnormal squared length, below 2^-511 h
+// as a length, is taken as 2^-511 h.
+__device__ inline double rsqrt_len(double x) {
+    const double xs = fmax(x, 0x1p-1022);
+    double r = __builtin_amdgcn_rsq(xs);
+    double e = fma(-xs * r, r, 1.0);
+    r = fma(0.5 * r, e, r);
+    e = fma(-xs * r, r, 1.0);
+    return fma(0.5 * r, e, r);
+}
 __device__ inline double sqrt_nr(double x) {
-    const double r = rsqrt_nr(x);
+    const double r = rsqrt_len(x);
     const double s = x * r;
     return fma(0.5 * r, fma(-s, s, x), s);
 }
 
 struct ExactMath {
-    __device__ double sqrt_(double x) const { return x > 0.0 ? sqrt_nr(x) : 0.0; }
+    // x >= 0 (sqrt_nr(0) = 0: the estimate is taken at the smallest normal)
+    __device__ double sqrt_(double x) const { return sqrt_nr(x); }
     __device__ double rsqrt_(double x) const { return rsqrt_nr(x); }
     __device__ double rcp_(double x) const { return 1.0 / x; }
     // angle between the ray to a clipped end at |y| = ay and the circle
@@ -82,11 +95,11 @@ struct ExactMath {
             den = p;
             sg = yA > 0.0 ? -1.0 : 1.0;
         }
-        return sg * log_pos(num / den);
+        return sg * log_pos(div_nr(num, den));
     }
     // length and inverse length of an edge vector
     __device__ void edge_norm(double len2, double &len, double &il) const {
-        il = rsqrt_nr(len2);
+        il = rsqrt_len(len2);
         len = len2 * il;
     }
     // policy for one edge at distance p (in units of h) from the particle

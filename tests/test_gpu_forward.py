@@ -445,3 +445,70 @@ def test_pair_status_flags_non_finite_pairs():
         assert np.array_equal(s.astype(bool), ~fin)
         assert s[np.isin(idx.cpu().numpy(), [10])].all()       # NaN field values propagate
         assert not s[~bad].any()
+
+
+def _custom_kernel(b, c_d, radius=1.0):
+    """A one-piece kernel with monomial coefficients b (degree len(b) - 1)."""
+    k = sb.SphbiKernel()
+    k.n_pieces = 1
+    k.degree[0] = len(b) - 1
+    k.radius[0] = radius
+    for i, v in enumerate(b):
+        k.b[0][i] = v
+    k.c_d = c_d
+    return k
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_zero_pattern_instantiations_linear_in_kernel(order):
+    """Wendland kernels have b_1 = b_3 = ... = 0 below their degree, and run
+    instantiations that leave those terms out; any other kernel runs the
+    generic ones.  The integrals are linear in the monomial coefficients, so
+    (C2 + q) = C2 + q: the left side runs the generic instantiation, C2 the
+    zero-pattern one and q alone the generic one again.  Same for the
+    adjoint.  On a small covering mesh."""
+    say(f"zero pattern: linearity in the kernel coefficients, P{order}")
+    wl = W.covering_workload(n_side=128, nx=16, ny=32, seed=8, kernel=0, field_order=order)
+    c2 = sb.kernel_preset(0)
+    b = [c2.b[0][i] for i in range(6)]
+    assert b[1] == 0.0
+    k_w = _custom_kernel(b, c2.c_d)
+    k_q = _custom_kernel([0.0, 1.0, 0.0, 0.0, 0.0, 0.0], c2.c_d)
+    k_s = _custom_kernel([b[0], 1.0] + b[2:], c2.c_d)
+    tpx, tpy, ttri, tnod = to_dev(wl.px, wl.py, wl.tri, wl.nodal)
+    off, idx = sb.pairlist(tpx, tpy, ttri, wl.h)
+    # default refinement: the few ill-conditioned pairs (kappa^3 of the cubic
+    # field on the aspect-ratio-20 mesh) in double-double, the rest through
+    # the instantiations under test
+    outs = [sb.integrate(k, wl.h, tpx, tpy, ttri, tnod, off, idx) for k in (k_w, k_q, k_s)]
+    ref = sb.integrate(0, wl.h, tpx, tpy, ttri, tnod, off, idx)
+    for a, r in zip(outs[0], ref):
+        assert torch.equal(a, r)                 # the custom copy of C2 takes the same instantiation
+    # rounding of three FP64 evaluations: the per-pair model 8 eps K kappa of
+    # the random-pairs test with K = 141 (C2, the worst of the three kernels),
+    # summed over each particle's pairs; a wrong instantiation errs by O(1)
+    offn, idxn = off.cpu().numpy(), idx.cpu().numpy()
+    n = wl.n_particles
+    own = np.repeat(np.arange(n), np.diff(offn))
+    rel = wl.tri[:, idxn].copy()
+    rel[0::2] -= wl.px[own]
+    rel[1::2] -= wl.py[own]
+    rel /= wl.h
+    amax = np.maximum(np.abs(wl.nodal[:, idxn]).max(0) * (3.0 if order == 3 else 1.0), 1.0)
+    bI = 3 * np.bincount(own, weights=8 * 1.1e-16 * KFAC[0] * conditioning(rel, order) * amax, minlength=n)
+    bG = bI * metrics.grad_scale(0, wl.h)
+    for comp, bnd in ((0, bI), (1, bG), (2, bG)):
+        lhs = outs[2][comp].cpu().numpy()
+        rhs = (outs[0][comp] + outs[1][comp]).cpu().numpy()
+        r = np.abs(lhs - rhs) / bnd
+        say(f"  component {comp}: worst |(C2 + q) - C2 - q| / bound {r.max():.2e}")
+        assert np.all(r <= 1.0)
+    g = [torch.randn(wl.n_particles, dtype=torch.float64, device=DEV,
+                     generator=torch.Generator(device=DEV).manual_seed(k)) for k in range(3)]
+    grads = [sb.integrate_backward(k, wl.h, tpx, tpy, ttri, tnod, off, idx, *g) for k in (k_w, k_q, k_s)]
+    for comp in range(4):
+        lhs = grads[2][comp]
+        rhs = grads[0][comp] + grads[1][comp]
+        err = float((lhs - rhs).abs().max() / lhs.abs().max())
+        say(f"  adjoint output {comp}: relative max deviation {err:.2e}")
+        assert err < 5e-11                       # measured 6e-12 (P3); a wrong instantiation errs by O(1)
