@@ -17,13 +17,23 @@ namespace sphbi {
 // pressure the compiler then spills it and reloads it from scratch memory
 // inside the polynomial.  sconst() hands the constant over through an opaque
 // scalar-register operand at the point of use, so it costs two scalar moves
-// (issued beside the vector work) and no vector register.
+// (issued beside the vector work; the hazard check adds a one-cycle wait after
+// the empty asm) and no vector register.  Measured on the cubic-field forward
+// kernel: 238 vector registers and no spills, against 256 and 68 bytes of
+// scratch spills per lane with plain constants; with the compiler's machine
+// loop-invariant code motion off, plain constants spill no more but cost a
+// vector move at each use (333 against 141 vector moves in the kernel).
 //
 // A translation unit that defines SPHBI_PLAIN_CONSTANTS before including this
-// header gets plain constants instead.  The adjoint does: its kernels run one
-// wave per SIMD whatever the constants cost, and in its largest fully
-// unrolled instantiations (cubic field) the opaque operand came out of the
-// compiler with wrong results, which plain constants do not.
+// header gets plain constants instead.  The adjoint's unit for constant and
+// cubic fields does: its kernels run one wave per SIMD, where the operand form
+// only adds instructions (0.608 against 0.589 ms on the C4/P3 differentiation
+// workload, bit-identical results).  An earlier version of that adjoint gave
+// wrong moments in its fully unrolled cubic instantiation with the operand
+// form; the current one passes every adjoint parity test with either form,
+// and the cause of the earlier failure was not found.  lit() now hands only
+// compile-time constants to the operand, so a lane-varying value can never
+// be read from a single lane.
 #ifdef SPHBI_PLAIN_CONSTANTS
 __device__ inline double sconst(double c) { return c; }
 #else

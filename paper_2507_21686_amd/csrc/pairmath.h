@@ -18,8 +18,12 @@ __host__ __device__ constexpr int pidx(int i, int j) { return (i + j) * (i + j +
 
 // An FP64 constant as an instruction operand: the values the hardware encodes
 // inline (0, +-1/2, +-1, +-2, +-4) stay literal, every other one is handed
-// over through a scalar register at its point of use (see sconst()).
+// over through a scalar register at its point of use (see sconst()).  Only a
+// value the compiler knows at compile time (after inlining and unrolling)
+// takes the scalar-register path; any other value is returned as it is, so
+// a lane-varying value can never be forced into a scalar register.
 __device__ inline double lit(double c) {
+    if (!__builtin_constant_p(c)) return c;
     const double a = fabs(c);
     return (a == 0.0 || a == 0.5 || a == 1.0 || a == 2.0 || a == 4.0) ? c : sconst(c);
 }
