@@ -323,7 +323,28 @@ def bench_surrogate(args, sb, torch, dev):
         rec = integ.prepare(g["tri"], g["nodal"])
         res[name] = event_time(torch, lambda: integ.integrate_prepared(g["px"], g["py"], T, rec, g["off"], g["idx"],
                                                                        out=out), n_steps, 2)
+    # speedup curve: the router calibrated for each stated error, the served
+    # result timed and its accepted-pair error measured on the evaluation mesh
+    speed = {}
+    for lv in sorted({1e-3, 3e-3, 1e-2, args.surrogate_level}):
+        t_lv = net.calibrate(calib, lv)
+        _, _, _, pp_lv, _, nf_lv = net.integrate(ev.h, g["px"], g["py"], g["tri"], g["nodal"], g["off"], g["idx"],
+                                                 model=model, threshold=t_lv, per_pair=True, ws=ws)
+        e_lv = torch.maximum((pp_lv[0] - ev.per_pair[0]).abs(),
+                             torch.maximum((pp_lv[1] - ev.per_pair[1]).abs(),
+                                           (pp_lv[2] - ev.per_pair[2]).abs()) * ev.h / net.sg)
+        ms_lv = event_time(torch, lambda: net.integrate(ev.h, g["px"], g["py"], g["tri"], g["nodal"], g["off"],
+                                                        g["idx"], model=model, threshold=t_lv, ws=ws), n_steps, 2)
+        speed[f"{lv:g}"] = {"ms": ms_lv, "flagged_fraction": int(nf_lv.item()) / ev.n,
+                            "max_error": float(e_lv.max()), "threshold": t_lv}
+    net.threshold = thr
     log(f"bench: network alone {ms_net:.3f} ms; flagged fraction by level {curve}")
+    for lv, v in speed.items():
+        v["speedup_vs_fp64"] = res["fp64"] / v["ms"]
+        log(f"bench: stated error {lv}: {v['ms']:.3f} ms, {v['flagged_fraction']:.2%} flagged, max error "
+            f"{v['max_error']:.2e}, {v['speedup_vs_fp64']:.2f}x the FP64 closed form")
+    # MFMA fraction of the network alone at which it would match the FP64 closed form
+    breakeven = MLP_FLOPS_PER_PAIR * ev.n / (res["fp64"] * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS
     log(f"bench: surrogate {ms_s:.3f} ms vs closed form {res['fp64']:.3f} ms (fp64) / {res['mixed']:.3f} ms (mixed), "
         f"flagged {flagged / ev.n:.3%}, max error {float(err.max()):.2e}; trained {info['steps']} steps in "
         f"{info['seconds']:.1f} s on {info['pairs']} pairs (data {t_data:.1f} s)")
@@ -339,6 +360,8 @@ def bench_surrogate(args, sb, torch, dev):
                          "flop_per_pair": MLP_FLOPS_PER_PAIR},
             "stated_error": args.surrogate_level, "miss_rate": 1e-4, "flagged_fraction": flagged / ev.n,
             "flagged_fraction_by_level": curve,
+            "speedup_curve": speed,
+            "mfma_fraction_to_match_fp64_closed_form": breakeven,
             "error": {"max": float(err.max()), "p50": float(q[0]), "p99": float(q[1]), "p99.99": float(q[2])},
             "threshold": thr,
             "training": {"steps": info["steps"], "seconds": info["seconds"], "pairs": info["pairs"], "batch": 16384},

@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kServeThreads, 2) void serve_kernel(
         const int64_t my_off = pid < N ? min(max(off[pid], (int64_t)0), q_end) : q_end;
         const int64_t my_end = pid < N ? min(max(off[pid + 1], my_off), q_end) : q_end;
         const int64_t q_begin = __shfl(my_off, 0);
-        float accI = 0.0f, accX = 0.0f, accY = 0.0f;      // network values (FP32 is ample)
+        double accI = 0.0, accX = 0.0, accY = 0.0;        // per-particle sums in FP64
         for (int64_t base = q_begin; base < q_end; base += 64) {
             const int64_t q = base + lane;
             const int64_t qq = q < q_end ? q : q_end - 1;
@@ -285,15 +285,15 @@ __global__ __launch_bounds__(kServeThreads, 2) void serve_kernel(
             }
             // router and de-standardisation
             const bool ok = inrange && y[3] <= threshold;
-            float vI = 0.0f, vX = 0.0f, vY = 0.0f;
+            double vI = 0.0, vX = 0.0, vY = 0.0;           // the pair's values: FP32 network outputs, summed in FP64
             if (ok) {
                 const float i0 = y[0] * sm.stdev[0] + sm.mean[0];
                 const float g1 = y[1] * sm.stdev[1] + sm.mean[1];
                 const float g2 = y[2] * sm.stdev[2] + sm.mean[2];
                 const float ah = Af * (float)invh;
-                vI = Af * i0;
-                vX = ah * (cf * g1 - sf * g2);
-                vY = ah * (sf * g1 + cf * g2);
+                vI = (double)(Af * i0);
+                vX = (double)(ah * (cf * g1 - sf * g2));
+                vY = (double)(ah * (sf * g1 + cf * g2));
             }
             if (q < q_end) {
                 flags[q] = (uint8_t)(valid && !ok);
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kServeThreads, 2) void serve_kernel(
             }
 #pragma unroll
             for (int d = 1; d < 64; d <<= 1) {
-                const float uI = __shfl_up(vI, d), uX = __shfl_up(vX, d), uY = __shfl_up(vY, d);
+                const double uI = __shfl_up(vI, d), uX = __shfl_up(vX, d), uY = __shfl_up(vY, d);
                 const int uo = __shfl_up(owner, d);
                 if (lane >= d && uo == owner) {
                     vI += uI;
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kServeThreads, 2) void serve_kernel(
             const int64_t s0 = my_off > base ? my_off : base;
             const int64_t s1 = my_end < base + 64 ? my_end : base + 64;
             const int src = s1 > s0 ? (int)(s1 - 1 - base) : 0;
-            const float rI = __shfl(vI, src), rX = __shfl(vX, src), rY = __shfl(vY, src);
+            const double rI = __shfl(vI, src), rX = __shfl(vX, src), rY = __shfl(vY, src);
             if (s1 > s0) {
                 accI += rI;
                 accX += rX;
@@ -324,9 +324,9 @@ __global__ __launch_bounds__(kServeThreads, 2) void serve_kernel(
             }
         }
         if (pid < N) {
-            I[pid] = (double)accI;
-            Gx[pid] = (double)accX;
-            Gy[pid] = (double)accY;
+            I[pid] = accI;
+            Gx[pid] = accX;
+            Gy[pid] = accY;
         }
     }
 }

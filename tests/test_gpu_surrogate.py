@@ -69,12 +69,16 @@ def test_features_bit_exact():
 
 
 def close_bf16(got, want, what):
-    """FP32 accumulation order may flip a bfloat16 rounding now and then."""
+    """The reference applies the same bfloat16 roundings, but the matrix cores
+    add in their own order, so a value on a rounding boundary may round the
+    other way now and then: one bfloat16 step (2^-8 of that value) in one
+    operand, carried through the later layers.  Measured over these tests:
+    maxima 4e-8 ... 7.2e-4 of the scale, medians below 3e-8."""
     got, want = np.asarray(got, np.float64), np.asarray(want, np.float64)
     scale = np.abs(want).max()
     err = np.abs(got - want) / scale
     say(f"  {what}: max {err.max():.2e} median {np.median(err):.2e} (scale {scale:.3e})")
-    assert err.max() < 2e-2 and np.median(err) < 1e-4, what
+    assert err.max() < 3e-3 and np.median(err) < 1e-6, what
 
 
 @pytest.mark.parametrize("B", [1, 77, 1000])
@@ -160,11 +164,12 @@ def test_serve_kernel_and_router():
     got = pp.cpu().numpy().T
     for k, name in enumerate(("I", "Gx", "Gy")):
         close_bf16(got[:, k], want[:, k], f"serve {name}")
-    # per-particle sums equal the per-pair values summed (network values are summed in FP32)
+    # per-particle sums equal the per-pair values summed (FP64 sums of the FP32 network values; only the
+    # order of the additions differs from numpy's)
     own = owners(off)
     for k, out in enumerate((I, Gx, Gy)):
         s = np.bincount(own, weights=got[:, k], minlength=wl.n_particles)
-        np.testing.assert_allclose(out.cpu().numpy(), s, rtol=1e-6, atol=1e-6 * np.abs(s).max())
+        np.testing.assert_allclose(out.cpu().numpy(), s, rtol=1e-13, atol=1e-13 * np.abs(s).max())
     # threshold between indicator values: exactly the pairs above it are flagged
     thr = float(np.median(ind))
     I2, Gx2, Gy2, pp2, flags2, nf2 = sb.surrogate_integrate(0, wl.h, px, py, tri, nod, off, idx, model, thr,
@@ -181,7 +186,7 @@ def test_serve_kernel_and_router():
     np.testing.assert_array_equal(got2[:, ~fl], got[~fl].T)
     for k, out in enumerate((I2, Gx2, Gy2)):
         s = np.bincount(own, weights=got2[k], minlength=wl.n_particles)
-        np.testing.assert_allclose(out.cpu().numpy(), s, rtol=1e-6, atol=1e-6 * np.abs(s).max())
+        np.testing.assert_allclose(out.cpu().numpy(), s, rtol=1e-13, atol=1e-13 * np.abs(s).max())
     # everything flagged: the closed form
     I3, Gx3, Gy3, _, flags3, nf3 = sb.surrogate_integrate(0, wl.h, px, py, tri, nod, off, idx, model, -1e30)
     I64, Gx64, Gy64 = sb.integrate(0, wl.h, px, py, tri, nod, off, idx)
