@@ -13,6 +13,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "refine.h"
 
 namespace sphbi {
@@ -40,19 +42,25 @@ __device__ __noinline__ void pair_dd(const KArgsDD &K, double x, double y, doubl
     oY = (double)Y;
 }
 
-// One wavefront owns 64 consecutive particles (a grid of a few blocks per
-// compute unit strides over the groups).  It sweeps its particles' pairs 64
-// at a time, one pair per lane, and appends the pairs to refine (every pair
-// with a valid triangle in the all-pairs mode, else those whose gate fires)
-// to a list in LDS, in pair order; whenever the list is full, and at the end,
-// the list is evaluated one pair per lane and every particle lane adds the
-// results of its own pairs in list order.  The lanes therefore run the costly
-// double-double pairs densely, whatever the pairs' distribution over the
-// particles, and the sums stay in pair order (deterministic).
+// One wavefront owns a window of `groups` x 64 consecutive particles (at most
+// kRefGroups; the launch sizes the windows so that the grid has about four
+// waves per compute unit, and the waves stride over the windows).  It sweeps the
+// window's pairs 64 at a time, one pair per lane, and appends the pairs to
+// refine (every pair with a valid triangle in the all-pairs mode, else those
+// whose gate fires) to a list in LDS, in pair order; whenever the list is
+// full, and at the end of the window, the list is evaluated one pair per lane
+// and the results are added to the window's per-particle sums in LDS in list
+// order.  The lanes therefore run the costly double-double pairs densely,
+// whatever the pairs' distribution over the particles: with a few refined
+// pairs per particle group, a whole window makes one evaluation round, whose
+// length is that of one double-double pair.  The sums stay in pair order
+// (deterministic).
 constexpr int kRefList = 128;
+constexpr int kRefGroups = 8;
+constexpr int kRefWindow = 64 * kRefGroups;
 
 template <int DEG, int ORDER>
-__global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate gate, bool all, double invh,
+__global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate gate, bool all, int groups, double invh,
                                                      int64_t N, const double *__restrict__ px,
                                                      const double *__restrict__ py, const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ tri_idx, int64_t P, int64_t T,
@@ -61,25 +69,26 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
                                                      double *__restrict__ Gx, double *__restrict__ Gy,
                                                      double *__restrict__ per_pair, uint8_t *__restrict__ status) {
     __shared__ int64_t s_q[kRefList];
-    __shared__ uint8_t s_own[kRefList];
+    __shared__ uint16_t s_own[kRefList];              // particle within the window
     __shared__ double s_res[kRefList][3];
+    __shared__ double s_acc[kRefWindow][3];
+    __shared__ uint8_t s_any[kRefWindow];
     if (!all && *gate.count == 0) return;       // the forward pass left out no pair
     const int lane = threadIdx.x;
-    for (int64_t p0 = (int64_t)blockIdx.x * 64; p0 < N; p0 += (int64_t)gridDim.x * 64) {
-        const int64_t pid = p0 + lane;
-        const int64_t plast = p0 + 64 < N ? p0 + 64 : N;
-        // the forward kernels' clamping of the CSR range
-        const int64_t q_end = min(max(off[plast], (int64_t)0), P);
-        const int64_t my_off = pid < N ? min(max(off[pid], (int64_t)0), q_end) : q_end;
-        const int64_t q_begin = __shfl(my_off, 0);
-        double aI = 0.0, aX = 0.0, aY = 0.0;
-        bool any = false;
+    const int64_t window = 64 * (int64_t)groups;
+    for (int64_t w0 = (int64_t)blockIdx.x * window; w0 < N; w0 += (int64_t)gridDim.x * window) {
+        for (int k = lane; k < window; k += 64) {
+            s_acc[k][0] = s_acc[k][1] = s_acc[k][2] = 0.0;
+            s_any[k] = 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         int n_list = 0;
-        // evaluates the listed pairs and adds them to their particles
+        // evaluates the listed pairs and adds them to their particles' sums
         auto flush = [&]() {
             for (int j = lane; j < n_list; j += 64) {
                 const int64_t q = s_q[j];
-                const int64_t ip = p0 + s_own[j];
+                const int64_t ip = w0 + s_own[j];
                 double vI, vX, vY;
                 pair_dd<DEG, ORDER>(K, px[ip], py[ip], invh, tri, nodal, T, tri_idx[q], vI, vX, vY);
                 s_res[j][0] = vI;
@@ -94,72 +103,89 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            for (int j = 0; j < n_list; ++j)
-                if (s_own[j] == lane) {
-                    aI += s_res[j][0];
-                    aX += s_res[j][1];
-                    aY += s_res[j][2];
-                    any = true;
+            // lane l adds the entries of the particles l, l + 64, ... in list order
+            for (int j = 0; j < n_list; ++j) {
+                const int own = s_own[j];
+                if ((own & 63) == lane) {
+                    s_acc[own][0] += s_res[j][0];
+                    s_acc[own][1] += s_res[j][1];
+                    s_acc[own][2] += s_res[j][2];
+                    s_any[own] = 1;
                 }
+            }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             n_list = 0;
         };
-        for (int64_t base = q_begin; base < q_end; base += 64) {
-            const int64_t q = base + lane;
-            const int64_t qq = q < q_end ? q : q_end - 1;
-            int lo = 0;                                // owner lane (the forward kernels' search)
+        for (int g = 0; g < groups; ++g) {
+            const int64_t p0 = w0 + 64 * g;
+            if (p0 >= N) break;
+            const int64_t pid = p0 + lane;
+            const int64_t plast = p0 + 64 < N ? p0 + 64 : N;
+            // the forward kernels' clamping of the CSR range
+            const int64_t q_end = min(max(off[plast], (int64_t)0), P);
+            const int64_t my_off = pid < N ? min(max(off[pid], (int64_t)0), q_end) : q_end;
+            const int64_t q_begin = __shfl(my_off, 0);
+            for (int64_t base = q_begin; base < q_end; base += 64) {
+                const int64_t q = base + lane;
+                const int64_t qq = q < q_end ? q : q_end - 1;
+                int lo = 0;                                // owner lane (the forward kernels' search)
 #pragma unroll
-            for (int step = 32; step >= 1; step >>= 1) {
-                const int64_t om = __shfl(my_off, lo + step < 64 ? lo + step : 63);
-                if (lo + step < 64 && om <= qq) lo += step;
-            }
-            bool take = false;
-            if (q < q_end) {
-                const int32_t t = tri_idx[q];
-                if (t >= 0 && t < T) {
-                    if (all) {
-                        take = true;
-                    } else {
-                        const int64_t ip = p0 + lo;
-                        double ax[3], ay[3];
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            ax[k] = (tri[(2 * k) * T + t] - px[ip]) * invh;
-                            ay[k] = (tri[(2 * k + 1) * T + t] - py[ip]) * invh;
-                        }
-                        take = gate.fires(ax, ay);
-                    }
-                } else if (all) {
-                    if (per_pair) per_pair[q] = per_pair[P + q] = per_pair[2 * P + q] = 0.0;
-                    if (status) status[q] = 0;
+                for (int step = 32; step >= 1; step >>= 1) {
+                    const int64_t om = __shfl(my_off, lo + step < 64 ? lo + step : 63);
+                    if (lo + step < 64 && om <= qq) lo += step;
                 }
+                bool take = false;
+                if (q < q_end) {
+                    const int32_t t = tri_idx[q];
+                    if (t >= 0 && t < T) {
+                        if (all) {
+                            take = true;
+                        } else {
+                            const int64_t ip = p0 + lo;
+                            double ax[3], ay[3];
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) {
+                                ax[k] = (tri[(2 * k) * T + t] - px[ip]) * invh;
+                                ay[k] = (tri[(2 * k + 1) * T + t] - py[ip]) * invh;
+                            }
+                            take = gate.fires(ax, ay);
+                        }
+                    } else if (all) {
+                        if (per_pair) per_pair[q] = per_pair[P + q] = per_pair[2 * P + q] = 0.0;
+                        if (status) status[q] = 0;
+                    }
+                }
+                const uint64_t mask = __ballot(take);
+                const int cnt = __popcll(mask);
+                if (cnt == 0) continue;
+                if (n_list + cnt > kRefList) flush();
+                if (take) {
+                    const int slot = n_list + __popcll(mask & ((1ull << lane) - 1));
+                    s_q[slot] = q;
+                    s_own[slot] = (uint16_t)(64 * g + lo);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                n_list += cnt;
             }
-            const uint64_t mask = __ballot(take);
-            const int cnt = __popcll(mask);
-            if (cnt == 0) continue;
-            if (n_list + cnt > kRefList) flush();
-            if (take) {
-                const int slot = n_list + __popcll(mask & ((1ull << lane) - 1));
-                s_q[slot] = q;
-                s_own[slot] = (uint8_t)lo;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            n_list += cnt;
         }
         if (n_list) flush();
-        if (pid < N) {
+        for (int k = lane; k < window; k += 64) {
+            const int64_t pid = w0 + k;
+            if (pid >= N) break;
             if (all) {
-                I[pid] = aI;
-                Gx[pid] = aX;
-                Gy[pid] = aY;
-            } else if (any) {
-                I[pid] += aI;
-                Gx[pid] += aX;
-                Gy[pid] += aY;
+                I[pid] = s_acc[k][0];
+                Gx[pid] = s_acc[k][1];
+                Gy[pid] = s_acc[k][2];
+            } else if (s_any[k]) {
+                I[pid] += s_acc[k][0];
+                Gx[pid] += s_acc[k][1];
+                Gy[pid] += s_acc[k][2];
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -168,16 +194,19 @@ void launch_refine_order(int deg, const KArgsDD &K, const RefineGate &g, bool al
                          const double *px, const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P,
                          int64_t T, const double *tri, const double *nodal, double *I, double *Gx, double *Gy,
                          double *per_pair, hipStream_t s, uint8_t *status) {
-    // a few waves per compute unit: enough to fill the chip when every pair
-    // is refined (the kernel runs one wave per SIMD), little to launch when
-    // none is
+    // about four waves per compute unit (the kernel runs one wave per SIMD):
+    // the windows grow with N up to kRefGroups groups, so that a few refined
+    // pairs per group still make dense evaluation rounds, and the grid still
+    // fills the chip when every pair is refined
     int dev = 0, n_cu = 256;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         n_cu = 256;
-    const int64_t want = (N + 63) / 64, cap = (int64_t)n_cu * 8;
+    const int64_t n_groups = (N + 63) / 64, target = 4 * (int64_t)n_cu;
+    const int groups = (int)std::min<int64_t>(kRefGroups, std::max<int64_t>(1, n_groups / target));
+    const int64_t want = (n_groups + groups - 1) / groups, cap = (int64_t)n_cu * 8;
     const unsigned blocks = (unsigned)(want < cap ? want : cap);
 #define SPHBI_REF(DG)                                                                                          \
-    hipLaunchKernelGGL((refine_kernel<DG, ORDER>), dim3(blocks), dim3(64), 0, s, K, g, all, invh, N, px, py, off, \
+    hipLaunchKernelGGL((refine_kernel<DG, ORDER>), dim3(blocks), dim3(64), 0, s, K, g, all, groups, invh, N, px, py, off, \
                        tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, status)
     if (deg <= 3) SPHBI_REF(3);
     else if (deg <= 5) SPHBI_REF(5);
