@@ -203,7 +203,9 @@ void launch_refine_order(int deg, const KArgsDD &K, const RefineGate &g, bool al
         n_cu = 256;
     const int64_t n_groups = (N + 63) / 64, target = 4 * (int64_t)n_cu;
     const int groups = (int)std::min<int64_t>(kRefGroups, std::max<int64_t>(1, n_groups / target));
-    const int64_t want = (n_groups + groups - 1) / groups, cap = (int64_t)n_cu * 8;
+    // (one round of waves: the kernel holds one wave per SIMD, and a launch
+    // that finds nothing to refine costs the dispatch of every block)
+    const int64_t want = (n_groups + groups - 1) / groups, cap = (int64_t)n_cu * 4;
     const unsigned blocks = (unsigned)(want < cap ? want : cap);
 #define SPHBI_REF(DG)                                                                                          \
     hipLaunchKernelGGL((refine_kernel<DG, ORDER>), dim3(blocks), dim3(64), 0, s, K, g, all, groups, invh, N, px, py, off, \

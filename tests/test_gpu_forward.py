@@ -390,7 +390,10 @@ def test_refine_modes():
     say("refine modes")
     wl = W.sliver_stress(seed=3, grid=8, kernel=1, field_order=3)
     cov = W.covering_workload(n_side=64, nx=8, ny=16, seed=2, kernel=1, field_order=3)
-    for w in (wl, cov):
+    # 160,000 particles: the refinement kernel's windows hold two groups of 64
+    # particles there, and the last window is ragged
+    big = W.covering_workload(n_side=400, nx=50, ny=100, seed=5, kernel=1, field_order=3)
+    for w in (wl, cov, big):
         tpx, tpy, ttri = to_dev(w.px, w.py, w.tri)
         off, idx = sb.pairlist(tpx, tpy, ttri, w.h)
         off, idx = off.cpu().numpy(), idx.cpu().numpy()
