@@ -7,7 +7,7 @@
 
 #include <math.h>
 
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 // plain FP64 constants in this unit (see sconst)
 #define SPHBI_PLAIN_CONSTANTS 1
@@ -85,8 +85,8 @@ __global__ void sort_keys(int64_t P, int64_t T, int64_t N, const int64_t *__rest
 size_t backward_workspace(int64_t T, int64_t P, int n_nodes) {
     const size_t NG = 6 + (size_t)n_nodes;
     size_t tmp = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                             (const int32_t *)nullptr, (int32_t *)nullptr, (int)(P > 0 ? P : 1));
+    (void)rocprim::radix_sort_pairs(nullptr, tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                    (const int32_t *)nullptr, (int32_t *)nullptr, (size_t)(P > 0 ? P : 1));
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t o = 0;
     o += al((size_t)(P > 0 ? P : 1) * NG * sizeof(double));      // per-pair gradients
@@ -119,8 +119,8 @@ int launch_backward(int order, int deg, int precision, double tau, const KArgs &
     int64_t *start = (int64_t *)w;
     w += al((size_t)(T + 1) * sizeof(int64_t));
     size_t tmp = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                             (const int32_t *)nullptr, (int32_t *)nullptr, (int)Pn);
+    (void)rocprim::radix_sort_pairs(nullptr, tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                    (const int32_t *)nullptr, (int32_t *)nullptr, (size_t)Pn);
     const double invh = 1.0 / h;
     const bool mixed = precision == SPHBI_MIXED;
     if (N > 0) {
@@ -148,7 +148,7 @@ int launch_backward(int order, int deg, int precision, double tau, const KArgs &
                            iota);
         int bits = 1;                                  // keys are in [0, T]
         while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)T) ++bits;
-        e = hipcub::DeviceRadixSort::SortPairs(w, tmp, keys_in, keys, iota, perm, (int)P, 0, bits, s);
+        e = rocprim::radix_sort_pairs(w, tmp, keys_in, keys, iota, perm, (size_t)P, 0u, (unsigned)bits, s);
         if (e != hipSuccess) { set_error("pair sort: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
     }
     hipLaunchKernelGGL(tri_starts, dim3((unsigned)((T + 1 + 255) / 256)), dim3(256), 0, s, P, T, keys, start);

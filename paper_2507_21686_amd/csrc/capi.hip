@@ -6,7 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "internal.h"
 #include "refine.h"
@@ -302,8 +302,10 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static int layout(const sphbi_grid *g, int64_t N, WsLayout *L) {
     const size_t ncell = (size_t)g->nx * g->ny;
     size_t t1 = 0, t2 = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, t1, (int *)nullptr, (int *)nullptr, (int)(ncell + 1));
-    (void)hipcub::DeviceScan::InclusiveSum(nullptr, t2, (int64_t *)nullptr, (int64_t *)nullptr, (int)(N > 0 ? N : 1));
+    (void)rocprim::exclusive_scan(nullptr, t1, (int *)nullptr, (int *)nullptr, 0, (size_t)(ncell + 1),
+                                  rocprim::plus<int>());
+    (void)rocprim::inclusive_scan(nullptr, t2, (int64_t *)nullptr, (int64_t *)nullptr, (size_t)(N > 0 ? N : 1),
+                                  rocprim::plus<int64_t>());
     size_t o = 0;
     L->cell_start = o; o = align256(o + (ncell + 1) * sizeof(int));
     L->cursor = o; o = align256(o + (ncell + 1) * sizeof(int));
@@ -423,7 +425,8 @@ int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t 
                            (unsigned long long *)nullptr, cursor);
     CHECK_HIP(hipGetLastError());
     size_t tb = L.scan_tmp_bytes;
-    CHECK_HIP(hipcub::DeviceScan::ExclusiveSum(w + L.scan_tmp, tb, cursor, cell_start, (int)(ncell + 1), s));
+    CHECK_HIP(rocprim::exclusive_scan(w + L.scan_tmp, tb, cursor, cell_start, 0, (size_t)(ncell + 1),
+                                      rocprim::plus<int>(), s));
     CHECK_HIP(hipMemsetAsync(cursor, 0, (ncell + 1) * sizeof(int), s));
     if (T > 0)
         hipLaunchKernelGGL(tri_ref_fill, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, T, tri, h,
@@ -435,7 +438,8 @@ int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t 
                            h * h, cell_start, items, offsets + 1);
         CHECK_HIP(hipGetLastError());
         tb = L.scan_tmp_bytes;
-        CHECK_HIP(hipcub::DeviceScan::InclusiveSum(w + L.scan_tmp, tb, offsets + 1, offsets + 1, (int)N, s));
+        CHECK_HIP(rocprim::inclusive_scan(w + L.scan_tmp, tb, offsets + 1, offsets + 1, (size_t)N,
+                                          rocprim::plus<int64_t>(), s));
     }
     CHECK_HIP(hipMemcpyAsync(n_pairs, offsets + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     CHECK_HIP(hipStreamSynchronize(s));

@@ -21,7 +21,7 @@
 //      its sums (one thread per run of a particle, so the result is
 //      deterministic without atomics).
 
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_select.hpp>
 #include <math.h>
 
 #include "features.h"
@@ -426,8 +426,8 @@ ServeWs carve_serve(void *base, int64_t T, int64_t P) {
     size_t cub_bytes = 0;
     // size query only (no device work); a failure leaves cub_bytes at 0 and
     // the compaction call reports it
-    (void)hipcub::DeviceSelect::Flagged(nullptr, cub_bytes, (int64_t *)nullptr, (uint8_t *)nullptr,
-                                        (int64_t *)nullptr, (int64_t *)nullptr, (int)(P > 0 ? P : 1));
+    (void)rocprim::select(nullptr, cub_bytes, (int64_t *)nullptr, (uint8_t *)nullptr, (int64_t *)nullptr,
+                          (int64_t *)nullptr, (size_t)(P > 0 ? P : 1));
     char *p = (char *)base;
     size_t o = 0;
     auto take = [&](size_t bytes) { char *r = p ? p + o : nullptr; o += al(bytes); return r; };
@@ -500,7 +500,7 @@ int surrogate_integrate(const KArgs &K, int deg, double h, int64_t N, const doub
     // compact the flagged pairs (pair order)
     hipLaunchKernelGGL(iota64_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, P, w.iota);
     size_t cb = w.cub_bytes;
-    e = hipcub::DeviceSelect::Flagged(w.cub, cb, w.iota, flags, w.list, w.count, (int)P, s);
+    e = rocprim::select(w.cub, cb, w.iota, flags, w.list, w.count, (size_t)P, s);
     if (e != hipSuccess) { set_error("flag compaction: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
     // field records for the fallback (P0: vertices + value)
     int rc = launch_prepare(0, T, tri, nodal, h, w.rec, s);
