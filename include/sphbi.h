@@ -139,8 +139,10 @@ const char *sphbi_last_error(void);
  * Synchronises `stream`.
  *
  * sphbi_pairlist_fill: writes tri_idx[0 .. n_pairs-1] using the offsets and
- * the grid left in `ws` by the count call.  Asynchronous.  cap is the length
- * of tri_idx; cap < n_pairs returns SPHBI_ECAPACITY.
+ * the grid, cell lists and per-particle candidate masks left in `ws` by the
+ * count call.  cap is the length of tri_idx; cap < offsets[N] returns
+ * SPHBI_ECAPACITY, for which it reads offsets[N] back and so synchronises
+ * `stream`.
  * ------------------------------------------------------------------- */
 typedef struct {
     double x0, y0, cell;

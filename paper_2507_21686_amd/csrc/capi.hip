@@ -198,55 +198,154 @@ __device__ inline void tri_cells(const GridDev &g, const double *__restrict__ tr
     if (!(fx1 >= 0.0) || !(fy1 >= 0.0) || !(fx0 <= g.nx - 1) || !(fy0 <= g.ny - 1)) { cx1 = cx0 - 1; cy1 = cy0 - 1; }
 }
 
-__global__ void tri_ref_count(GridDev g, int64_t T, const double *__restrict__ tri, double h,
-                              unsigned long long *__restrict__ total, int *__restrict__ cell_count) {
+// Grid registrations of the whole mesh (the plan's size query): one atomic
+// per block of 256 triangles (atomics on one address serialise).
+__global__ __launch_bounds__(256) void tri_ref_total(GridDev g, int64_t T, const double *__restrict__ tri, double h,
+                                                     unsigned long long *__restrict__ total) {
+    __shared__ unsigned long long s_part[4];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    int cx0, cx1, cy0, cy1;
-    tri_cells(g, tri, T, t, h, cx0, cx1, cy0, cy1);
-    if (cx1 < cx0 || cy1 < cy0) return;
-    if (total) atomicAdd(total, (unsigned long long)(cx1 - cx0 + 1) * (unsigned long long)(cy1 - cy0 + 1));
-    if (cell_count)
-        for (int cy = cy0; cy <= cy1; ++cy)
-            for (int cx = cx0; cx <= cx1; ++cx) atomicAdd(&cell_count[cy * g.nx + cx], 1);
+    unsigned long long n = 0;
+    if (t < T) {
+        int cx0, cx1, cy0, cy1;
+        tri_cells(g, tri, T, t, h, cx0, cx1, cy0, cy1);
+        if (cx1 >= cx0 && cy1 >= cy0) n = (unsigned long long)(cx1 - cx0 + 1) * (unsigned long long)(cy1 - cy0 + 1);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) n += __shfl_xor(n, d);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long b = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+        if (b) atomicAdd(total, b);
+    }
 }
 
-__global__ void tri_ref_fill(GridDev g, int64_t T, const double *__restrict__ tri, double h,
-                             const int *__restrict__ cell_start, int *__restrict__ cursor,
-                             int *__restrict__ items, int64_t n_refs) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
-    int cx0, cx1, cy0, cy1;
-    tri_cells(g, tri, T, t, h, cx0, cx1, cy0, cy1);
-    for (int cy = cy0; cy <= cy1; ++cy)
-        for (int cx = cx0; cx <= cx1; ++cx) {
-            const int c = cy * g.nx + cx;
-            const int slot = cell_start[c] + atomicAdd(&cursor[c], 1);
-            if (slot < n_refs) items[slot] = (int)t;
+// Registration of every triangle in the cells its support box covers,
+// 16 lanes per triangle (a triangle covers about 30 cells on a mesh of
+// triangles a few h across): with one thread per triangle the serial chain
+// of atomics was the cost.  FILL = false counts per cell; FILL = true writes
+// the triangle into the cell's slot range (in an order the atomics decide;
+// cell_sort restores ascending order).
+template <bool FILL>
+__global__ void tri_ref_cells(GridDev g, int64_t T, const double *__restrict__ tri, double h,
+                              int *__restrict__ cursor, const int *__restrict__ cell_start, int *__restrict__ items,
+                              int64_t n_refs) {
+    const int64_t nthreads = T * 16;
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < nthreads;
+         gid += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = gid >> 4;
+        const int sub = (int)(gid & 15);
+        int cx0, cx1, cy0, cy1;
+        tri_cells(g, tri, T, t, h, cx0, cx1, cy0, cy1);
+        if (cx1 < cx0 || cy1 < cy0) continue;
+        const int wx = cx1 - cx0 + 1;
+        const int64_t n = (int64_t)wx * (cy1 - cy0 + 1);
+        for (int64_t k = sub; k < n; k += 16) {
+            const int c = (cy0 + (int)(k / wx)) * g.nx + cx0 + (int)(k % wx);
+            if (FILL) {
+                const int slot = cell_start[c] + atomicAdd(&cursor[c], 1);
+                if (slot < n_refs) items[slot] = (int)t;
+            } else {
+                atomicAdd(&cursor[c], 1);
+            }
         }
+    }
 }
 
-// squared distance from (x, y) to triangle t (0 inside)
-__device__ inline double dist2_tri(double x, double y, const double *__restrict__ tri, int64_t T, int64_t t) {
-    const double x0 = tri[t], y0 = tri[T + t], x1 = tri[2 * T + t], y1 = tri[3 * T + t];
-    const double x2 = tri[4 * T + t], y2 = tri[5 * T + t];
+// Every cell's triangles in ascending index order, so that a particle's
+// pairs come out sorted (a particle reads the list of its own cell only).
+// Here and in the pair kernels a cell list is cut at n_refs, the size of
+// the items array: registrations beyond it (a grid planned for other
+// triangles or another h) are dropped, never read or written.
+//
+// A block takes 256 consecutive cells, whose lists are one contiguous range
+// of items: staged in LDS when it fits (the usual ~10 entries per cell),
+// sorted in place in global memory otherwise.  Shell sort with Ciura's gaps:
+// insertion sort for short lists, no quadratic worst case for a cell that
+// many large triangles cover.
+__device__ inline void shell_sort(int *v, int n) {
+    constexpr int gaps[8] = {701, 301, 132, 57, 23, 10, 4, 1};
+    for (int gi = 0; gi < 8; ++gi) {
+        const int gap = gaps[gi];
+        if (gap >= n) continue;
+        for (int i = gap; i < n; ++i) {
+            const int x = v[i];
+            int j = i;
+            for (; j >= gap && v[j - gap] > x; j -= gap) v[j] = v[j - gap];
+            v[j] = x;
+        }
+    }
+}
+
+constexpr int kSortLds = 8192;       // ints of LDS per block (32 KB)
+
+__global__ __launch_bounds__(256) void cell_sort(int64_t ncell, const int *__restrict__ cell_start,
+                                                 int *__restrict__ items, int64_t n_refs) {
+    __shared__ int s_items[kSortLds];
+    const int64_t c0 = (int64_t)blockIdx.x * 256;
+    const int64_t c = c0 + threadIdx.x;
+    const int64_t cl = c0 + 256 < ncell ? c0 + 256 : ncell;
+    const int a0 = (int)min((int64_t)cell_start[c0], n_refs);
+    const int a1 = (int)min((int64_t)cell_start[cl], n_refs);
+    const bool staged = a1 - a0 <= kSortLds;           // the same for the whole block
+    if (staged) {
+        for (int k = threadIdx.x; k < a1 - a0; k += 256) s_items[k] = items[a0 + k];
+        __syncthreads();
+    }
+    if (c < ncell) {
+        const int a = cell_start[c];
+        const int b = (int)min((int64_t)cell_start[c + 1], n_refs);
+        if (b - a >= 2) shell_sort(staged ? s_items + (a - a0) : items + a, b - a);
+    }
+    if (staged) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < a1 - a0; k += 256) items[a0 + k] = s_items[k];
+    }
+}
+
+// Block order for the particle kernels: workgroups go to the eight XCDs in
+// turn, so block b runs on XCD b mod 8.  Mapping each XCD's blocks to one
+// contiguous range of particles keeps the triangles and cell lists that
+// range reads in that XCD's own L2.  A bijection on [0, nb).
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+    const int64_t q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// Triangle vertices as one 64-byte record each (x0 y0 x1 y1 x2 y2 and two
+// pad doubles), so that a candidate test reads one cache line instead of six
+// strided doubles.
+__global__ void tri_pack(int64_t T, const double *__restrict__ tri, double4 *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    out[2 * t] = make_double4(tri[t], tri[T + t], tri[2 * T + t], tri[3 * T + t]);
+    out[2 * t + 1] = make_double4(tri[4 * T + t], tri[5 * T + t], 0.0, 0.0);
+}
+
+// Whether (x, y) is within sqrt(h2) of triangle t: the squared distance
+// (0 inside) compared with h2.  (A bounding-box rejection first, which
+// removes a third of the candidates on a covering mesh, measured no faster:
+// the kernel is bound by the candidates' 64-byte loads, not the tests.)
+__device__ inline bool near_tri(double x, double y, const double4 *__restrict__ tv, int t, double h2) {
+    const double4 va = tv[2 * t], vb = tv[2 * t + 1];
+    const double x0 = va.x, y0 = va.y, x1 = va.z, y1 = va.w, x2 = vb.x, y2 = vb.y;
     const double c0 = (x1 - x0) * (y - y0) - (y1 - y0) * (x - x0);
     const double c1 = (x2 - x1) * (y - y1) - (y2 - y1) * (x - x1);
     const double c2 = (x0 - x2) * (y - y2) - (y0 - y2) * (x - x2);
-    if ((c0 >= 0.0 && c1 >= 0.0 && c2 >= 0.0) || (c0 <= 0.0 && c1 <= 0.0 && c2 <= 0.0)) return 0.0;
+    if ((c0 >= 0.0 && c1 >= 0.0 && c2 >= 0.0) || (c0 <= 0.0 && c1 <= 0.0 && c2 <= 0.0)) return true;
     double best = INFINITY;
     const double ex[3] = {x0, x1, x2}, ey[3] = {y0, y1, y2};
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-        const double ax = ex[e], ay = ey[e], bx = ex[(e + 1) % 3], by = ey[(e + 1) % 3];
-        const double dx = bx - ax, dy = by - ay;
+        const double ax = ex[e], ay = ey[e], ux = ex[(e + 1) % 3], uy = ey[(e + 1) % 3];
+        const double dx = ux - ax, dy = uy - ay;
         const double L = dx * dx + dy * dy;
         double s = L > 0.0 ? ((x - ax) * dx + (y - ay) * dy) / L : 0.0;
         s = fmin(fmax(s, 0.0), 1.0);
         const double qx = ax + s * dx - x, qy = ay + s * dy - y;
         best = fmin(best, qx * qx + qy * qy);
     }
-    return best;
+    return best < h2;
 }
 
 __device__ inline int particle_cell(const GridDev &g, double x, double y) {
@@ -255,51 +354,61 @@ __device__ inline int particle_cell(const GridDev &g, double x, double y) {
     return cy * g.nx + cx;
 }
 
+// Pairs per particle.  A particle whose cell lists at most 64 triangles also
+// keeps the bit mask of those that pass, so that pair_fill need not test them
+// again.
 __global__ void pair_count(GridDev g, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
-                           int64_t T, const double *__restrict__ tri, double h2, const int *__restrict__ cell_start,
-                           const int *__restrict__ items, int64_t *__restrict__ counts) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                           const double4 *__restrict__ tv, double h2, const int *__restrict__ cell_start,
+                           const int *__restrict__ items, int64_t n_refs, int64_t *__restrict__ counts,
+                           uint64_t *__restrict__ mask) {
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const double x = px[i], y = py[i];
     const int c = particle_cell(g, x, y);
+    const int k0 = cell_start[c], k1 = (int)min((int64_t)cell_start[c + 1], n_refs);
     int64_t n = 0;
-    for (int k = cell_start[c]; k < cell_start[c + 1]; ++k)
-        if (dist2_tri(x, y, tri, T, items[k]) < h2) ++n;
+    uint64_t m = 0;
+    for (int k = k0; k < k1; ++k)
+        if (near_tri(x, y, tv, items[k], h2)) {
+            ++n;
+            m |= (uint64_t)1 << ((k - k0) & 63);
+        }
     counts[i] = n;
+    mask[i] = m;
 }
 
+// The cell lists are sorted, so every particle's pairs come out in ascending
+// triangle order.
 __global__ void pair_fill(GridDev g, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
-                          int64_t T, const double *__restrict__ tri, double h2, const int *__restrict__ cell_start,
-                          const int *__restrict__ items, const int64_t *__restrict__ offsets,
-                          int32_t *__restrict__ tri_idx, int64_t cap) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                          const double4 *__restrict__ tv, double h2, const int *__restrict__ cell_start,
+                          const int *__restrict__ items, int64_t n_refs, const uint64_t *__restrict__ mask,
+                          const int64_t *__restrict__ offsets, int32_t *__restrict__ tri_idx, int64_t cap) {
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const double x = px[i], y = py[i];
     const int c = particle_cell(g, x, y);
-    const int64_t q0 = offsets[i], q1 = offsets[i + 1] < cap ? offsets[i + 1] : cap;
-    int64_t q = q0;
-    for (int k = cell_start[c]; k < cell_start[c + 1] && q < q1; ++k) {
-        const int t = items[k];
-        if (dist2_tri(x, y, tri, T, t) < h2) tri_idx[q++] = t;
-    }
-    // ascending triangle order (cell lists are filled with atomics)
-    for (int64_t a = q0 + 1; a < q; ++a) {
-        const int32_t v = tri_idx[a];
-        int64_t b = a - 1;
-        while (b >= q0 && tri_idx[b] > v) { tri_idx[b + 1] = tri_idx[b]; --b; }
-        tri_idx[b + 1] = v;
+    const int64_t q1 = offsets[i + 1] < cap ? offsets[i + 1] : cap;
+    const int k0 = cell_start[c], k1 = (int)min((int64_t)cell_start[c + 1], n_refs);
+    int64_t q = offsets[i] > 0 ? offsets[i] : 0;
+    if (k1 - k0 <= 64) {
+        for (uint64_t m = mask[i]; m && q < q1; m &= m - 1) tri_idx[q++] = items[k0 + __builtin_ctzll(m)];
+    } else {
+        for (int k = k0; k < k1 && q < q1; ++k) {
+            const int t = items[k];
+            if (near_tri(x, y, tv, t, h2)) tri_idx[q++] = t;
+        }
     }
 }
 
 __global__ void write_zero_i64(int64_t *p) { *p = 0; }
 
 struct WsLayout {
-    size_t cell_start, cursor, items, scan_tmp, scan_tmp_bytes, total;
+    size_t cell_start, cursor, items, tri4, mask, scan_tmp, scan_tmp_bytes, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static int layout(const sphbi_grid *g, int64_t N, WsLayout *L) {
+static int layout(const sphbi_grid *g, int64_t N, int64_t T, WsLayout *L) {
     const size_t ncell = (size_t)g->nx * g->ny;
     size_t t1 = 0, t2 = 0;
     (void)rocprim::exclusive_scan(nullptr, t1, (int *)nullptr, (int *)nullptr, 0, (size_t)(ncell + 1),
@@ -310,6 +419,8 @@ static int layout(const sphbi_grid *g, int64_t N, WsLayout *L) {
     L->cell_start = o; o = align256(o + (ncell + 1) * sizeof(int));
     L->cursor = o; o = align256(o + (ncell + 1) * sizeof(int));
     L->items = o; o = align256(o + (size_t)(g->n_refs > 0 ? g->n_refs : 1) * sizeof(int));
+    L->tri4 = o; o = align256(o + (size_t)(T > 0 ? T : 1) * 8 * sizeof(double));
+    L->mask = o; o = align256(o + (size_t)(N > 0 ? N : 1) * sizeof(uint64_t));
     L->scan_tmp = o;
     L->scan_tmp_bytes = t1 > t2 ? t1 : t2;
     o = align256(o + L->scan_tmp_bytes);
@@ -384,8 +495,7 @@ int sphbi_pairlist_plan(int64_t N, const double *px, const double *py, int64_t T
                                   ((N + 255) / 256 < 1024 ? (N + 255) / 256 : 1024));
         hipLaunchKernelGGL(write_zero_i64, dim3(1), dim3(1), 0, s, (int64_t *)tot);
         GridDev g = to_dev(grid);
-        hipLaunchKernelGGL(tri_ref_count, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, T, tri, h, tot,
-                           (int *)nullptr);
+        hipLaunchKernelGGL(tri_ref_total, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, T, tri, h, tot);
         CHECK_HIP(hipGetLastError());
         unsigned long long n = 0;
         CHECK_HIP(hipMemcpyAsync(&n, tot, sizeof(n), hipMemcpyDeviceToHost, s));
@@ -399,7 +509,7 @@ int sphbi_pairlist_plan(int64_t N, const double *px, const double *py, int64_t T
     }
     if (tmp) CHECK_HIP(hipFreeAsync(tmp, s));
     WsLayout L;
-    layout(grid, N, &L);
+    layout(grid, N, T, &L);
     *ws_bytes = L.total;
     return SPHBI_OK;
 }
@@ -412,30 +522,40 @@ int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t 
     if (!grid || !n_pairs || !offsets) { set_error("grid/offsets/n_pairs is NULL"); return SPHBI_EINVAL; }
     if (grid->nx <= 0 || grid->ny <= 0 || !(grid->cell > 0)) { set_error("grid not planned"); return SPHBI_EINVAL; }
     WsLayout L;
-    layout(grid, N, &L);
+    layout(grid, N, T, &L);
     if (!ws || ws_bytes < L.total) { set_error("workspace too small (%zu < %zu)", ws_bytes, L.total); return SPHBI_ENOWORKSPACE; }
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
     int *cell_start = (int *)(w + L.cell_start), *cursor = (int *)(w + L.cursor), *items = (int *)(w + L.items);
+    double4 *tri4 = (double4 *)(w + L.tri4);
     const size_t ncell = (size_t)grid->nx * grid->ny;
     GridDev g = to_dev(grid);
+    // 16 lanes per triangle, grid-stride beyond 2^16 blocks
+    const int64_t rb = (T * 16 + 255) / 256;
+    const unsigned ref_blocks = (unsigned)(rb < 65536 ? (rb > 0 ? rb : 1) : 65536);
     CHECK_HIP(hipMemsetAsync(cursor, 0, (ncell + 1) * sizeof(int), s));
-    if (T > 0)
-        hipLaunchKernelGGL(tri_ref_count, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, T, tri, h,
-                           (unsigned long long *)nullptr, cursor);
+    if (T > 0) {
+        hipLaunchKernelGGL(tri_pack, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, T, tri, tri4);
+        hipLaunchKernelGGL(tri_ref_cells<false>, dim3(ref_blocks), dim3(256), 0, s, g, T, tri, h, cursor,
+                           (const int *)nullptr, (int *)nullptr, (int64_t)0);
+    }
     CHECK_HIP(hipGetLastError());
     size_t tb = L.scan_tmp_bytes;
     CHECK_HIP(rocprim::exclusive_scan(w + L.scan_tmp, tb, cursor, cell_start, 0, (size_t)(ncell + 1),
                                       rocprim::plus<int>(), s));
     CHECK_HIP(hipMemsetAsync(cursor, 0, (ncell + 1) * sizeof(int), s));
-    if (T > 0)
-        hipLaunchKernelGGL(tri_ref_fill, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, T, tri, h,
-                           cell_start, cursor, items, grid->n_refs);
+    if (T > 0) {
+        hipLaunchKernelGGL(tri_ref_cells<true>, dim3(ref_blocks), dim3(256), 0, s, g, T, tri, h, cursor, cell_start,
+                           items, grid->n_refs);
+        hipLaunchKernelGGL(cell_sort, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, (int64_t)ncell,
+                           cell_start, items, grid->n_refs);
+    }
     CHECK_HIP(hipGetLastError());
     CHECK_HIP(hipMemsetAsync(offsets, 0, sizeof(int64_t), s));
     if (N > 0) {
-        hipLaunchKernelGGL(pair_count, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g, N, px, py, T, tri,
-                           h * h, cell_start, items, offsets + 1);
+        hipLaunchKernelGGL(pair_count, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g, N, px, py,
+                           (const double4 *)tri4, h * h, cell_start, items, grid->n_refs, offsets + 1,
+                           (uint64_t *)(w + L.mask));
         CHECK_HIP(hipGetLastError());
         tb = L.scan_tmp_bytes;
         CHECK_HIP(rocprim::inclusive_scan(w + L.scan_tmp, tb, offsets + 1, offsets + 1, (size_t)N,
@@ -453,7 +573,7 @@ int sphbi_pairlist_fill(int64_t N, const double *px, const double *py, int64_t T
     if (rc) return rc;
     if (!grid || !offsets || (cap > 0 && !tri_idx)) { set_error("grid/offsets/tri_idx is NULL"); return SPHBI_EINVAL; }
     WsLayout L;
-    layout(grid, N, &L);
+    layout(grid, N, T, &L);
     if (!ws || ws_bytes < L.total) { set_error("workspace too small"); return SPHBI_ENOWORKSPACE; }
     hipStream_t s = (hipStream_t)stream;
     int64_t total = 0;
@@ -463,8 +583,10 @@ int sphbi_pairlist_fill(int64_t N, const double *px, const double *py, int64_t T
     char *w = (char *)ws;
     GridDev g = to_dev(grid);
     if (N > 0)
-        hipLaunchKernelGGL(pair_fill, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g, N, px, py, T, tri,
-                           h * h, (const int *)(w + L.cell_start), (const int *)(w + L.items), offsets, tri_idx, cap);
+        hipLaunchKernelGGL(pair_fill, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g, N, px, py,
+                           (const double4 *)(w + L.tri4), h * h, (const int *)(w + L.cell_start),
+                           (const int *)(w + L.items), grid->n_refs, (const uint64_t *)(w + L.mask), offsets,
+                           tri_idx, cap);
     CHECK_HIP(hipGetLastError());
     return SPHBI_OK;
 }

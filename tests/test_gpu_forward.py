@@ -81,6 +81,29 @@ def test_pairlist_covering_and_slivers():
     check_pairlist(W.sliver_stress(seed=3, grid=8))
 
 
+def test_pairlist_crowded_cells():
+    """Large overlapping triangles, so that every cell lists hundreds of them
+    (the per-cell sort's long gaps): same pairs as the brute-force oracle,
+    ascending within each particle, and the same arrays from a second build."""
+    say("pairlist crowded cells")
+    rng = np.random.default_rng(11)
+    h = 0.05
+    c = rng.uniform(0.0, 1.0, size=(2, 600))
+    tri = np.empty((6, 600))
+    for v in range(3):
+        ang = rng.uniform(0.0, 2 * np.pi, 600)
+        rad = rng.uniform(0.1, 0.6, 600)
+        tri[2 * v] = c[0] + rad * np.cos(ang)
+        tri[2 * v + 1] = c[1] + rad * np.sin(ang)
+    wl = W.Workload("crowded", rng.uniform(0.0, 1.0, 3000), rng.uniform(0.0, 1.0, 3000), tri,
+                    np.ones((1, 600)), h, 0, meta={})
+    off, idx, _ = check_pairlist(wl)
+    assert off[-1] > 40 * wl.n_particles          # about 60 triangles per particle
+    tpx, tpy, ttri = to_dev(wl.px, wl.py, wl.tri)
+    off2, idx2 = sb.pairlist(tpx, tpy, ttri, h)
+    assert np.array_equal(off2.cpu().numpy(), off) and np.array_equal(idx2.cpu().numpy(), idx)
+
+
 def test_pairlist_edge_cases():
     say("pairlist edge cases")
     # no particles, no triangles, all far away
