@@ -673,13 +673,18 @@ namespace sphbi {
 
 // Default thresholds of the conditioning gate on Kf kappa^order (see
 // sphbi_opts), G = G0 (141 / Kf)^1.25, 141 being Kf of Wendland C2.  Fitted
-// to the per-particle errors measured against the double-double path on
-// covering meshes (aspect ratio 20, cubic and linear fields) and on 0.5-degree
-// slivers with particles 1e-8..1e-2 h from edges and vertices: with
-// G0 = 3e6 the FP64 pass stays within 1e-12 of the scale for Wendland C2, C4
-// and C6 (the Wendland C2 covering mesh of 2^20 particles has no pair above
-// it); with G0 = 1e9 the mixed pass stays within 1e-6.
-constexpr double kGateFP64 = 3e6, kGateMixed = 1e9;
+// to the per-pair errors measured against the double-double path on
+// covering meshes (aspect ratio 20 and 60, cubic and linear fields) and on
+// 0.5-degree slivers with particles 1e-8..1e-2 h from edges and vertices.
+// With G0 = 3e6 for cubic fields the FP64 pass stays within 1e-12 of the
+// scale for Wendland C2, C4 and C6 (the Wendland C2 covering mesh of 2^20
+// particles has no pair above it).  Linear fields lose less (kappa^1): with
+// G0 = 3e7 every preset kernel stays within 1e-12 on those workloads (largest
+// kept error 5.2e-13, Wendland C6 on a covering mesh, where 3e6 sent two
+// thirds of the pairs to double-double for errors already below 6e-13),
+// while the C6 slivers are still all refined.  With G0 = 1e9 the mixed pass
+// stays within 1e-6.
+constexpr double kGateFP64 = 3e6, kGateFP64Linear = 3e7, kGateMixed = 1e9;
 
 // Kf = sum_p sum_k |b_pk| R_p^(k+2)/(k+2) / |sum_p sum_k b_pk R_p^(k+2)/(k+2)|:
 // the cancellation of the kernel's monomial form in the integral over the
@@ -699,7 +704,10 @@ RefineGate make_gate(const sphbi_opts &o, int order, const KArgs &K) {
     if (o.refine != SPHBI_REFINE_AUTO || order == 0) return refine_off();
     const double kf = kernel_cancellation(K);
     const double thr = o.refine_gate > 0.0 ? o.refine_gate
-                                           : (o.precision == SPHBI_MIXED ? kGateMixed : kGateFP64) * pow(141.0 / kf, 1.25);
+                                           : (o.precision == SPHBI_MIXED ? kGateMixed
+                                              : order == 1                   ? kGateFP64Linear
+                                                                             : kGateFP64) *
+                                                 pow(141.0 / kf, 1.25);
     if (!isfinite(thr)) return refine_off();
     const double g = thr / kf;
     return RefineGate{order, 0, g * g};

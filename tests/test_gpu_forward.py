@@ -406,6 +406,29 @@ def test_forward_precision_stress_full_size_cubic(kid):
     assert eI <= 1e-12 and eG <= 1e-12
 
 
+@pytest.mark.parametrize("kid", [1, 2])
+def test_linear_field_gate(kid):
+    """Linear fields on a covering mesh (aspect ratio up to 60) with the
+    high-cancellation kernels: the default gate keeps FP64 within 1e-12 of the
+    double-double evaluation per particle, refining at most a few pairs (the
+    linear fields' threshold; the cubic fields' one refined two thirds of the
+    Wendland C6 pairs here)."""
+    wl = W.covering_workload(n_side=192, nx=24, ny=48, seed=7, kernel=kid, field_order=1, ar_target=60.0)
+    say(f"linear-field gate kid={kid}: N={wl.n_particles}")
+    tpx, tpy, ttri = to_dev(wl.px, wl.py, wl.tri)
+    off, idx = sb.pairlist(tpx, tpy, ttri, wl.h)
+    off, idx = off.cpu().numpy(), idx.cpu().numpy()
+    args = (kid, wl.h, wl.px, wl.py, wl.tri, wl.nodal, off, idx)
+    auto = run_gpu(*args, per_pair=True)
+    dd = run_gpu(*args, per_pair=True, refine=sb.REFINE_ALL)
+    plain = run_gpu(*args, per_pair=True, refine=sb.REFINE_OFF)
+    refined = int(np.any(auto[3] != plain[3], axis=0).sum())
+    t = error_table(kid, wl.h, float(np.abs(wl.nodal).max()), auto[:3], dd[:3])
+    say(f"  {refined} of {idx.size} pairs refined; default vs double-double {t}")
+    assert t["I"][0] <= 1e-12 and t["G"][0] <= 1e-12
+    assert refined <= 1e-3 * idx.size
+
+
 def test_refine_modes():
     """AUTO refines exactly the gated pairs: its per-pair values equal the
     double-double ones there and the FP64 ones elsewhere, bit for bit; the
