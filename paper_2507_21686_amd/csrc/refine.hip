@@ -22,11 +22,11 @@ namespace {
 
 // One pair in double-double: the field record of the triangle is rebuilt from
 // the exact input doubles and the pair is evaluated by the same closed form
-// as the FP64 kernels.
+// as the FP64 kernels, its edge loop starting at vertex rot (see near_edges).
 template <int DEG, int ORDER>
 __device__ __noinline__ void pair_dd(const KArgsDD &K, double x, double y, double invh, const double *__restrict__ tri,
-                                     const double *__restrict__ nodal, int64_t T, int64_t t, double &oI, double &oX,
-                                     double &oY) {
+                                     const double *__restrict__ nodal, int64_t T, int64_t t, int rot, double &oI,
+                                     double &oX, double &oY) {
     constexpr int NN = ORDER == 0 ? 1 : (ORDER == 1 ? 3 : 10);
     dd v[6], A[10];
 #pragma unroll
@@ -36,7 +36,7 @@ __device__ __noinline__ void pair_dd(const KArgsDD &K, double x, double y, doubl
     dd r[kRecDoubles];
     prepare_record<ORDER, dd>(v, A, invh, r);
     dd I, X, Y;
-    pair_fwd<DEG, ORDER, dd, DDMath, 1>(K, DDMath(), 0.0, dd(x), dd(y), invh, r, I, X, Y);
+    pair_fwd_rot<DEG, ORDER, dd, DDMath, 1>(K, DDMath(), 0.0, dd(x), dd(y), invh, r, rot, I, X, Y);
     oI = (double)I;
     oX = (double)X;
     oY = (double)Y;
@@ -53,7 +53,10 @@ __device__ __noinline__ void pair_dd(const KArgsDD &K, double x, double y, doubl
 // order.  The lanes therefore run the costly double-double pairs densely,
 // whatever the pairs' distribution over the particles: with a few refined
 // pairs per particle group, a whole window makes one evaluation round, whose
-// length is that of one double-double pair.  The sums stay in pair order
+// length is that of one double-double pair.  As in the sorted FP64 kernel, a
+// list is evaluated in the order of its pairs' near-edge counts, most first,
+// each triangle's edge loop starting at its near edges, so that the lanes of
+// a round take the same branches.  The sums stay in pair order
 // (deterministic).
 constexpr int kRefList = 128;
 constexpr int kRefGroups = 8;
@@ -70,11 +73,14 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
                                                      double *__restrict__ per_pair, uint8_t *__restrict__ status) {
     __shared__ int64_t s_q[kRefList];
     __shared__ uint16_t s_own[kRefList];              // particle within the window
+    __shared__ uint8_t s_key[kRefList];               // near-edge count << 2 | rotation
+    __shared__ uint8_t s_perm[kRefList];              // evaluation order
     __shared__ double s_res[kRefList][3];
     __shared__ double s_acc[kRefWindow][3];
     __shared__ uint8_t s_any[kRefWindow];
     if (!all && *gate.count == 0) return;       // the forward pass left out no pair
     const int lane = threadIdx.x;
+    const double Rout = K.R[K.npieces - 1], R2 = Rout * Rout;
     const int64_t window = 64 * (int64_t)groups;
     for (int64_t w0 = (int64_t)blockIdx.x * window; w0 < N; w0 += (int64_t)gridDim.x * window) {
         for (int k = lane; k < window; k += 64) {
@@ -86,11 +92,38 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
         int n_list = 0;
         // evaluates the listed pairs and adds them to their particles' sums
         auto flush = [&]() {
-            for (int j = lane; j < n_list; j += 64) {
+            // counting sort of the list by near-edge count, most first
+            {
+                int cnt[4] = {0, 0, 0, 0}, start[4];
+                for (int c0 = 0; c0 < n_list; c0 += 64) {
+                    const int j = c0 + lane;
+                    const int nr = j < n_list ? s_key[j] >> 2 : -1;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) cnt[b] += __popcll(__ballot(nr == b));
+                }
+                start[3] = 0;
+                start[2] = cnt[3];
+                start[1] = start[2] + cnt[2];
+                start[0] = start[1] + cnt[1];
+                for (int c0 = 0; c0 < n_list; c0 += 64) {
+                    const int j = c0 + lane;
+                    const int nr = j < n_list ? s_key[j] >> 2 : -1;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const uint64_t m = __ballot(nr == b);
+                        if (nr == b) s_perm[start[b] + __popcll(m & ((1ull << lane) - 1))] = (uint8_t)j;
+                        start[b] += __popcll(m);
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (int i = lane; i < n_list; i += 64) {
+                const int j = s_perm[i];
                 const int64_t q = s_q[j];
                 const int64_t ip = w0 + s_own[j];
                 double vI, vX, vY;
-                pair_dd<DEG, ORDER>(K, px[ip], py[ip], invh, tri, nodal, T, tri_idx[q], vI, vX, vY);
+                pair_dd<DEG, ORDER>(K, px[ip], py[ip], invh, tri, nodal, T, tri_idx[q], s_key[j] & 3, vI, vX, vY);
                 s_res[j][0] = vI;
                 s_res[j][1] = vX;
                 s_res[j][2] = vY;
@@ -136,20 +169,22 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
                     if (lo + step < 64 && om <= qq) lo += step;
                 }
                 bool take = false;
+                int key = 0;
                 if (q < q_end) {
                     const int32_t t = tri_idx[q];
                     if (t >= 0 && t < T) {
-                        if (all) {
-                            take = true;
-                        } else {
-                            const int64_t ip = p0 + lo;
-                            double ax[3], ay[3];
+                        const int64_t ip = p0 + lo;
+                        double ax[3], ay[3];
 #pragma unroll
-                            for (int k = 0; k < 3; ++k) {
-                                ax[k] = (tri[(2 * k) * T + t] - px[ip]) * invh;
-                                ay[k] = (tri[(2 * k + 1) * T + t] - py[ip]) * invh;
-                            }
-                            take = gate.fires(ax, ay);
+                        for (int k = 0; k < 3; ++k) {
+                            ax[k] = (tri[(2 * k) * T + t] - px[ip]) * invh;
+                            ay[k] = (tri[(2 * k + 1) * T + t] - py[ip]) * invh;
+                        }
+                        take = all || gate.fires(ax, ay);
+                        if (take) {
+                            int rot = 0;
+                            const int nr = near_edges(ax, ay, R2, rot);
+                            key = nr << 2 | rot;
                         }
                     } else if (all) {
                         if (per_pair) per_pair[q] = per_pair[P + q] = per_pair[2 * P + q] = 0.0;
@@ -164,6 +199,7 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
                     const int slot = n_list + __popcll(mask & ((1ull << lane) - 1));
                     s_q[slot] = q;
                     s_own[slot] = (uint16_t)(64 * g + lo);
+                    s_key[slot] = (uint8_t)key;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 __builtin_amdgcn_wave_barrier();
