@@ -591,7 +591,7 @@ int sphbi_pairlist_fill(int64_t N, const double *px, const double *py, int64_t T
     return SPHBI_OK;
 }
 
-size_t sphbi_integrate_workspace(int64_t T) { return records_bytes(T) + 256; }
+size_t sphbi_integrate_workspace(int64_t T) { return records_bytes(T) + 256 + dd_records_bytes(T); }
 
 static int check_common(const sphbi_kernel *kernel, const sphbi_opts *opts, sphbi_opts *o, double h, int32_t n_nodes,
                         int64_t N, int64_t T, int64_t n_pairs) {
@@ -630,8 +630,8 @@ static int field_prepare(double h, int32_t n_nodes, int64_t T, const double *tri
     if (T == 0) return SPHBI_OK;
     if (!tri || !nodal || !rec) { set_error("triangle/nodal/record arrays are NULL"); return SPHBI_EINVAL; }
     if (!aligned8(tri) || !aligned8(nodal) || !aligned8(rec)) { set_error("arrays must be 8-byte aligned"); return SPHBI_EINVAL; }
-    if (rec_bytes < sphbi_integrate_workspace(T)) {
-        set_error("record buffer too small (%zu < %zu)", rec_bytes, sphbi_integrate_workspace(T));
+    if (rec_bytes < records_bytes(T) + 256) {               // the records and the refinement counter
+        set_error("record buffer too small (%zu < %zu)", rec_bytes, records_bytes(T) + 256);
         return SPHBI_ENOWORKSPACE;
     }
     const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
@@ -724,9 +724,14 @@ int integrate_run(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, 
     const KArgs K = make_kargs(kernel, &deg);
     const int order = n_nodes == 1 ? 0 : (n_nodes == 3 ? 1 : 3);
     hipStream_t s = (hipStream_t)stream;
+    // the double-double records of the refinement pass, behind the records
+    // and the counter when the storage holds them (else built per pair)
+    double *rec_dd = rec_bytes >= records_bytes(T) + 256 + dd_records_bytes(T)
+                         ? (double *)((char *)rec + records_bytes(T) + 256)
+                         : nullptr;
     if (o.refine == SPHBI_REFINE_ALL)
         return launch_refine(order, deg, K, refine_off(), true, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, I,
-                             Gx, Gy, per_pair, s, o.pair_status);
+                             Gx, Gy, per_pair, s, o.pair_status, rec_dd);
     // the refinement counter sits behind the records
     unsigned long long *count = (unsigned long long *)((char *)rec + records_bytes(T));
     RefineGate gate = T > 0 ? make_gate(o, order, K) : refine_off();
@@ -737,7 +742,7 @@ int integrate_run(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, 
                         I, Gx, Gy, per_pair, s, o.pair_status);
     if (rc || !gate.order) return rc;
     return launch_refine(order, deg, K, gate, false, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, I, Gx, Gy,
-                         per_pair, s, o.pair_status);
+                         per_pair, s, o.pair_status, rec_dd);
 }
 
 int check_integrate_args(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,

@@ -107,6 +107,9 @@ int launch_prepare(int order, int64_t T, const double *tri, const double *nodal,
                    hipStream_t s, unsigned long long *count = nullptr);
 // bytes of the record buffer of T triangles; the refinement counter follows
 inline size_t records_bytes(int64_t T) { return (((size_t)(T > 0 ? T : 1) * kRecDoubles * sizeof(double)) + 255) & ~(size_t)255; }
+// bytes of the double-double records of the refinement pass (twice the
+// doubles of a record), behind the records and the counter
+inline size_t dd_records_bytes(int64_t T) { return records_bytes(T) * 2; }
 struct RefineGate;
 // the whole forward call on prepared-record storage rec: records, FP64 or
 // mixed pass, and the double-double refinement the options ask for

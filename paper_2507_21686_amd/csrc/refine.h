@@ -59,9 +59,11 @@ KArgsDD make_kargs_dd(const KArgs &K);
 // The refinement pass: all = true writes I, Gx, Gy (and per_pair) from the
 // double-double evaluation of every pair; all = false adds the pairs whose
 // gate fires to the outputs of a forward pass run with the same gate.
+// rec_dd (dd_records_bytes(T) bytes, or null): storage for the triangles'
+// double-double records, built once per call instead of once per pair.
 int launch_refine(int order, int deg, const KArgs &K, const RefineGate &gate, bool all, double h, int64_t N,
                   const double *px, const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P,
                   int64_t T, const double *tri, const double *nodal, double *I, double *Gx, double *Gy,
-                  double *per_pair, hipStream_t s, uint8_t *status = nullptr);
+                  double *per_pair, hipStream_t s, uint8_t *status = nullptr, double *rec_dd = nullptr);
 
 }  // namespace sphbi

@@ -20,21 +20,60 @@
 namespace sphbi {
 namespace {
 
-// One pair in double-double: the field record of the triangle is rebuilt from
-// the exact input doubles and the pair is evaluated by the same closed form
-// as the FP64 kernels, its edge loop starting at vertex rot (see near_edges).
-template <int DEG, int ORDER>
-__device__ __noinline__ void pair_dd(const KArgsDD &K, double x, double y, double invh, const double *__restrict__ tri,
-                                     const double *__restrict__ nodal, int64_t T, int64_t t, int rot, double &oI,
-                                     double &oX, double &oY) {
+// The field record of triangle t in double-double, from the exact input
+// doubles.
+template <int ORDER>
+__device__ inline void record_dd(double invh, const double *__restrict__ tri, const double *__restrict__ nodal,
+                                 int64_t T, int64_t t, dd *r) {
     constexpr int NN = ORDER == 0 ? 1 : (ORDER == 1 ? 3 : 10);
     dd v[6], A[10];
 #pragma unroll
     for (int k = 0; k < 6; ++k) v[k] = dd(tri[k * T + t]);
 #pragma unroll
     for (int k = 0; k < 10; ++k) A[k] = dd(k < NN ? nodal[k * T + t] : 0.0);
-    dd r[kRecDoubles];
     prepare_record<ORDER, dd>(v, A, invh, r);
+}
+
+// Every triangle's double-double record, once per call (stored as hi, lo
+// pairs, kRecDoubles of them per triangle), so that the pairs of a triangle
+// do not each rebuild it.  It pays only when the refinement kernel's waves
+// evaluate several lists each: with fewer than dense_min refined pairs (one
+// list per wave) every wave's time is the latency of one list, and building
+// the records first would only add the latency of one record.  Both kernels
+// read the forward pass's count and take the same decision.
+template <int ORDER>
+__global__ __launch_bounds__(256) void prepare_dd_kernel(RefineGate gate, bool all, unsigned long long dense_min,
+                                                         double invh, int64_t T, const double *__restrict__ tri,
+                                                         const double *__restrict__ nodal, double *__restrict__ rec_dd) {
+    if (!all && *gate.count < dense_min) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    dd r[kRecDoubles];
+    record_dd<ORDER>(invh, tri, nodal, T, t, r);
+    double *o = rec_dd + t * 2 * kRecDoubles;
+#pragma unroll
+    for (int k = 0; k < kRecDoubles; ++k) {
+        o[2 * k] = r[k].hi;
+        o[2 * k + 1] = r[k].lo;
+    }
+}
+
+// One pair in double-double: the field record of the triangle (from rec_dd,
+// or rebuilt from the exact input doubles when rec_dd is null) and the pair
+// evaluated by the same closed form as the FP64 kernels, its edge loop
+// starting at vertex rot (see near_edges).
+template <int DEG, int ORDER>
+__device__ __noinline__ void pair_dd(const KArgsDD &K, double x, double y, double invh, const double *__restrict__ tri,
+                                     const double *__restrict__ nodal, const double *__restrict__ rec_dd, int64_t T,
+                                     int64_t t, int rot, double &oI, double &oX, double &oY) {
+    dd r[kRecDoubles];
+    if (rec_dd) {
+        const double *o = rec_dd + t * 2 * kRecDoubles;
+#pragma unroll
+        for (int k = 0; k < kRecDoubles; ++k) r[k] = dd(o[2 * k], o[2 * k + 1]);
+    } else {
+        record_dd<ORDER>(invh, tri, nodal, T, t, r);
+    }
     dd I, X, Y;
     pair_fwd_rot<DEG, ORDER, dd, DDMath, 1>(K, DDMath(), 0.0, dd(x), dd(y), invh, r, rot, I, X, Y);
     oI = (double)I;
@@ -70,7 +109,9 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
                                                      const double *__restrict__ tri,
                                                      const double *__restrict__ nodal, double *__restrict__ I,
                                                      double *__restrict__ Gx, double *__restrict__ Gy,
-                                                     double *__restrict__ per_pair, uint8_t *__restrict__ status) {
+                                                     double *__restrict__ per_pair, uint8_t *__restrict__ status,
+                                                     const double *__restrict__ rec_dd_in,
+                                                     unsigned long long dense_min) {
     __shared__ int64_t s_q[kRefList];
     __shared__ uint16_t s_own[kRefList];              // particle within the window
     __shared__ uint8_t s_key[kRefList];               // near-edge count << 2 | rotation
@@ -79,6 +120,8 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
     __shared__ double s_acc[kRefWindow][3];
     __shared__ uint8_t s_any[kRefWindow];
     if (!all && *gate.count == 0) return;       // the forward pass left out no pair
+    // the records prepare_dd_kernel built (the same test), else built per pair
+    const double *rec_dd = (all || *gate.count >= dense_min) ? rec_dd_in : nullptr;
     const int lane = threadIdx.x;
     const double Rout = K.R[K.npieces - 1], R2 = Rout * Rout;
     const int64_t window = 64 * (int64_t)groups;
@@ -123,7 +166,8 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
                 const int64_t q = s_q[j];
                 const int64_t ip = w0 + s_own[j];
                 double vI, vX, vY;
-                pair_dd<DEG, ORDER>(K, px[ip], py[ip], invh, tri, nodal, T, tri_idx[q], s_key[j] & 3, vI, vX, vY);
+                pair_dd<DEG, ORDER>(K, px[ip], py[ip], invh, tri, nodal, rec_dd, T, tri_idx[q], s_key[j] & 3, vI, vX,
+                                    vY);
                 s_res[j][0] = vI;
                 s_res[j][1] = vX;
                 s_res[j][2] = vY;
@@ -229,7 +273,7 @@ template <int ORDER>
 void launch_refine_order(int deg, const KArgsDD &K, const RefineGate &g, bool all, double invh, int64_t N,
                          const double *px, const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P,
                          int64_t T, const double *tri, const double *nodal, double *I, double *Gx, double *Gy,
-                         double *per_pair, hipStream_t s, uint8_t *status) {
+                         double *per_pair, hipStream_t s, uint8_t *status, double *rec_dd) {
     // about four waves per compute unit (the kernel runs one wave per SIMD):
     // the windows grow with N up to kRefGroups groups, so that a few refined
     // pairs per group still make dense evaluation rounds, and the grid still
@@ -243,9 +287,13 @@ void launch_refine_order(int deg, const KArgsDD &K, const RefineGate &g, bool al
     // that finds nothing to refine costs the dispatch of every block)
     const int64_t want = (n_groups + groups - 1) / groups, cap = (int64_t)n_cu * 4;
     const unsigned blocks = (unsigned)(want < cap ? want : cap);
+    const unsigned long long dense_min = 64ull * blocks;      // more refined pairs than one list per wave
+    if (rec_dd && T > 0)
+        hipLaunchKernelGGL((prepare_dd_kernel<ORDER>), dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, all,
+                           dense_min, invh, T, tri, nodal, rec_dd);
 #define SPHBI_REF(DG)                                                                                          \
     hipLaunchKernelGGL((refine_kernel<DG, ORDER>), dim3(blocks), dim3(64), 0, s, K, g, all, groups, invh, N, px, py, off, \
-                       tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, status)
+                       tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, status, rec_dd, dense_min)
     if (deg <= 3) SPHBI_REF(3);
     else if (deg <= 5) SPHBI_REF(5);
     else if (deg <= 8) SPHBI_REF(8);
@@ -289,18 +337,18 @@ KArgsDD make_kargs_dd(const KArgs &K) {
 int launch_refine(int order, int deg, const KArgs &K, const RefineGate &gate, bool all, double h, int64_t N,
                   const double *px, const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P,
                   int64_t T, const double *tri, const double *nodal, double *I, double *Gx, double *Gy,
-                  double *per_pair, hipStream_t s, uint8_t *status) {
+                  double *per_pair, hipStream_t s, uint8_t *status, double *rec_dd) {
     if (N == 0) return SPHBI_OK;
     const KArgsDD D = make_kargs_dd(K);
     const double invh = 1.0 / h;
     if (order == 0)
-        launch_refine_order<0>(deg, D, gate, all, invh, N, px, py, off, tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, s, status);
+        launch_refine_order<0>(deg, D, gate, all, invh, N, px, py, off, tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, s, status, rec_dd);
     else if (order == 1)
         launch_refine_order<1>(deg, D, gate, all, invh, N, px, py, off, tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, s,
-                               status);
+                               status, rec_dd);
     else
         launch_refine_order<3>(deg, D, gate, all, invh, N, px, py, off, tri_idx, P, T, tri, nodal, I, Gx, Gy, per_pair, s,
-                               status);
+                               status, rec_dd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("refine launch: %s", hipGetErrorString(e)); return SPHBI_EDEVICE; }
     return SPHBI_OK;

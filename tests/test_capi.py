@@ -82,8 +82,9 @@ def test_bad_arguments_rejected_without_device():
 
 def test_workspace_size():
     # 128 B records per triangle (rounded up to 256 B), then 256 B for the refinement counter
-    assert sb.lib().sphbi_integrate_workspace(1000) == 1000 * 16 * 8 + 256
-    assert sb.lib().sphbi_integrate_workspace(1001) == 1002 * 16 * 8 + 256
+    # records (128 B per triangle, in 256-B steps), the counter, double-double records
+    assert sb.lib().sphbi_integrate_workspace(1000) == 3 * 1000 * 16 * 8 + 256
+    assert sb.lib().sphbi_integrate_workspace(1001) == 3 * 1002 * 16 * 8 + 256
     assert sb.lib().sphbi_integrate_workspace(0) >= 8
 
 
