@@ -18,7 +18,7 @@ int main(void) {
     sphbi_default_opts(&o);
     EXPECT(o.precision == SPHBI_FP64 && o.refine == SPHBI_REFINE_AUTO && o.pair_status == NULL);
     sphbi_default_opts(NULL);
-    EXPECT(sphbi_integrate_workspace(1000) == 1000 * 128 + 256);
+    EXPECT(sphbi_integrate_workspace(1000) == 3 * 1000 * 128 + 256);   /* records, counter, double-double records */
     double buf[64] = {0};
     double *p = buf;
     sphbi_kernel_preset(0, &k);
