@@ -198,14 +198,75 @@ __device__ inline void tri_cells(const GridDev &g, const double *__restrict__ tr
     if (!(fx1 >= 0.0) || !(fy1 >= 0.0) || !(fx0 <= g.nx - 1) || !(fy0 <= g.ny - 1)) { cx1 = cx0 - 1; cy1 = cy0 - 1; }
 }
 
-// Grid registrations of the whole mesh (the plan's size query): one atomic
-// per block of 256 triangles (atomics on one address serialise).
-__global__ __launch_bounds__(256) void tri_ref_total(GridDev g, int64_t T, const double *__restrict__ tri, double h,
-                                                     unsigned long long *__restrict__ total) {
+// The plan on the device, so that the host waits once: the particles'
+// bounding box from the per-block partials, and from it the grid exactly as
+// the host states it in sphbi_grid (cell = h, or extent / 4096 when that is
+// larger; nx, ny from the extents).  A non-finite box gives an empty grid
+// (the host then reports the coordinates).
+struct PlanOut {
+    double bb[4];
+    double x0, y0, cell;
+    int nx, ny;
+    unsigned long long total;
+};
+
+__global__ __launch_bounds__(256) void plan_grid(int nb, const double *__restrict__ part, double h,
+                                                 PlanOut *__restrict__ out) {
+    __shared__ double s[4][256];
+    double v[4] = {INFINITY, INFINITY, -INFINITY, -INFINITY};
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        v[0] = fmin(v[0], part[4 * b]);
+        v[1] = fmin(v[1], part[4 * b + 1]);
+        v[2] = fmax(v[2], part[4 * b + 2]);
+        v[3] = fmax(v[3], part[4 * b + 3]);
+    }
+    for (int k = 0; k < 4; ++k) s[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            s[1][threadIdx.x] = fmin(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+            s[2][threadIdx.x] = fmax(s[2][threadIdx.x], s[2][threadIdx.x + w]);
+            s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double b0 = s[0][0], b1 = s[1][0], b2 = s[2][0], b3 = s[3][0];
+        out->bb[0] = b0; out->bb[1] = b1; out->bb[2] = b2; out->bb[3] = b3;
+        out->total = 0;
+        if (isfinite(b0) && isfinite(b1) && isfinite(b2) && isfinite(b3)) {
+            const double ext = fmax(b2 - b0, b3 - b1);
+            double cell = h;
+            if (ext / cell > 4096.0) cell = ext / 4096.0;
+            out->x0 = b0;
+            out->y0 = b1;
+            out->cell = cell;
+            out->nx = (int)floor((b2 - b0) / cell) + 1;
+            out->ny = (int)floor((b3 - b1) / cell) + 1;
+        } else {
+            out->x0 = out->y0 = 0.0;
+            out->cell = h;
+            out->nx = out->ny = 0;
+        }
+    }
+}
+
+// Grid registrations of the whole mesh (the plan's size query) on the
+// device-side grid: one atomic per block of 256 triangles (atomics on one
+// address serialise).  A triangle covers at most 4097^2 cells.
+__global__ __launch_bounds__(256) void plan_refs(PlanOut *__restrict__ pg, int64_t T, const double *__restrict__ tri,
+                                                 double h) {
     __shared__ unsigned long long s_part[4];
+    GridDev g;
+    g.x0 = pg->x0;
+    g.y0 = pg->y0;
+    g.icell = 1.0 / pg->cell;
+    g.nx = pg->nx;
+    g.ny = pg->ny;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long n = 0;
-    if (t < T) {
+    if (t < T && g.nx > 0 && g.ny > 0) {
         int cx0, cx1, cy0, cy1;
         tri_cells(g, tri, T, t, h, cx0, cx1, cy0, cy1);
         if (cx1 >= cx0 && cy1 >= cy0) n = (unsigned long long)(cx1 - cx0 + 1) * (unsigned long long)(cy1 - cy0 + 1);
@@ -216,7 +277,7 @@ __global__ __launch_bounds__(256) void tri_ref_total(GridDev g, int64_t T, const
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned long long b = s_part[0] + s_part[1] + s_part[2] + s_part[3];
-        if (b) atomicAdd(total, b);
+        if (b) atomicAdd(&pg->total, b);
     }
 }
 
@@ -400,8 +461,6 @@ __global__ void pair_fill(GridDev g, int64_t N, const double *__restrict__ px, c
     }
 }
 
-__global__ void write_zero_i64(int64_t *p) { *p = 0; }
-
 struct WsLayout {
     size_t cell_start, cursor, items, tri4, mask, scan_tmp, scan_tmp_bytes, total;
 };
@@ -459,53 +518,38 @@ int sphbi_pairlist_plan(int64_t N, const double *px, const double *py, int64_t T
     if (!grid || !ws_bytes) { set_error("grid/ws_bytes outputs are NULL"); return SPHBI_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
     memset(grid, 0, sizeof(*grid));
-    double bb[4] = {0.0, 0.0, 0.0, 0.0};
     void *tmp = nullptr;
     if (N > 0) {
         const int nb = (int)((N + 255) / 256 < 1024 ? (N + 255) / 256 : 1024);
-        CHECK_HIP(hipMallocAsync(&tmp, sizeof(double) * 4 * nb + sizeof(unsigned long long), s));
+        CHECK_HIP(hipMallocAsync(&tmp, sizeof(double) * 4 * nb + sizeof(PlanOut), s));
+        PlanOut *po = (PlanOut *)((char *)tmp + sizeof(double) * 4 * nb);
         hipLaunchKernelGGL(bbox_partial, dim3(nb), dim3(256), 0, s, N, px, py, (double *)tmp);
+        hipLaunchKernelGGL(plan_grid, dim3(1), dim3(256), 0, s, nb, (const double *)tmp, h, po);
+        if (T > 0) hipLaunchKernelGGL(plan_refs, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, po, T, tri, h);
         CHECK_HIP(hipGetLastError());
-        double *hp = (double *)malloc(sizeof(double) * 4 * nb);
-        CHECK_HIP(hipMemcpyAsync(hp, tmp, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, s));
+        PlanOut ho;
+        CHECK_HIP(hipMemcpyAsync(&ho, po, sizeof(ho), hipMemcpyDeviceToHost, s));
         CHECK_HIP(hipStreamSynchronize(s));
-        bb[0] = INFINITY; bb[1] = INFINITY; bb[2] = -INFINITY; bb[3] = -INFINITY;
-        for (int b = 0; b < nb; ++b) {
-            bb[0] = fmin(bb[0], hp[4 * b]); bb[1] = fmin(bb[1], hp[4 * b + 1]);
-            bb[2] = fmax(bb[2], hp[4 * b + 2]); bb[3] = fmax(bb[3], hp[4 * b + 3]);
-        }
-        free(hp);
-        if (!isfinite(bb[0]) || !isfinite(bb[1]) || !isfinite(bb[2]) || !isfinite(bb[3])) {
+        if (!isfinite(ho.bb[0]) || !isfinite(ho.bb[1]) || !isfinite(ho.bb[2]) || !isfinite(ho.bb[3])) {
             (void)hipFreeAsync(tmp, s);
             set_error("non-finite particle coordinates");
             return SPHBI_EINVAL;
         }
-    }
-    const double ext = fmax(bb[2] - bb[0], bb[3] - bb[1]);
-    double cell = h;
-    if (ext / cell > 4096.0) cell = ext / 4096.0;
-    grid->x0 = bb[0];
-    grid->y0 = bb[1];
-    grid->cell = cell;
-    grid->nx = (int)floor((bb[2] - bb[0]) / cell) + 1;
-    grid->ny = (int)floor((bb[3] - bb[1]) / cell) + 1;
-    grid->n_refs = 0;
-    if (N > 0 && T > 0) {
-        unsigned long long *tot = (unsigned long long *)((char *)tmp + sizeof(double) * 4 *
-                                  ((N + 255) / 256 < 1024 ? (N + 255) / 256 : 1024));
-        hipLaunchKernelGGL(write_zero_i64, dim3(1), dim3(1), 0, s, (int64_t *)tot);
-        GridDev g = to_dev(grid);
-        hipLaunchKernelGGL(tri_ref_total, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, T, tri, h, tot);
-        CHECK_HIP(hipGetLastError());
-        unsigned long long n = 0;
-        CHECK_HIP(hipMemcpyAsync(&n, tot, sizeof(n), hipMemcpyDeviceToHost, s));
-        CHECK_HIP(hipStreamSynchronize(s));
-        if (n > (unsigned long long)INT32_MAX) {
+        if (ho.total > (unsigned long long)INT32_MAX) {
             (void)hipFreeAsync(tmp, s);
             set_error("grid registrations exceed 2^31");
             return SPHBI_EUNSUPPORTED;
         }
-        grid->n_refs = (int64_t)n;
+        grid->x0 = ho.x0;
+        grid->y0 = ho.y0;
+        grid->cell = ho.cell;
+        grid->nx = ho.nx;
+        grid->ny = ho.ny;
+        grid->n_refs = (int64_t)ho.total;
+    } else {
+        // no particles: the one-cell grid at the origin
+        grid->cell = h;
+        grid->nx = grid->ny = 1;
     }
     if (tmp) CHECK_HIP(hipFreeAsync(tmp, s));
     WsLayout L;

@@ -115,6 +115,10 @@ def test_pairlist_edge_cases():
     tpx, tpy, ttri = to_dev(np.array([0.1]), np.array([0.2]), np.zeros((6, 0)))
     off, idx = sb.pairlist(tpx, tpy, ttri, 0.3)
     assert off.cpu().numpy().tolist() == [0, 0]
+    # an infinite coordinate makes the bounding box non-finite: rejected by the plan
+    tpx, tpy, ttri = to_dev(np.array([0.1, np.inf]), np.array([0.2, 0.3]), tri)
+    with pytest.raises(sb.SphbiError, match="non-finite"):
+        sb.pairlist(tpx, tpy, ttri, 0.3)
 
 
 # ------------------------------------------------------------------ forward
