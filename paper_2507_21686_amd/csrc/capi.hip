@@ -376,11 +376,39 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
 // Triangle vertices as one 64-byte record each (x0 y0 x1 y1 x2 y2 and two
 // pad doubles), so that a candidate test reads one cache line instead of six
 // strided doubles.
-__global__ void tri_pack(int64_t T, const double *__restrict__ tri, double4 *__restrict__ out) {
+//
+// Also a 32-byte FP32 copy relative to the grid origin (x0 y0 x1 y1 x2 y2,
+// a flag, a pad), which decides most candidates with half the loads:
+// flag 1 when every coordinate lies within +-m of the origin (m bounds the
+// particles' coordinates too) and every edge is at least h long, so that the
+// FP32 distance, and the FP32 inside test for a point within h, are within
+// the margin the count pass allows for; else 0, and the candidate takes the
+// FP64 test.
+__global__ void tri_pack(GridDev g, double m, double h, int64_t T, const double *__restrict__ tri,
+                         double4 *__restrict__ out, float4 *__restrict__ out32) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
-    out[2 * t] = make_double4(tri[t], tri[T + t], tri[2 * T + t], tri[3 * T + t]);
-    out[2 * t + 1] = make_double4(tri[4 * T + t], tri[5 * T + t], 0.0, 0.0);
+    double v[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = tri[k * T + t];
+    out[2 * t] = make_double4(v[0], v[1], v[2], v[3]);
+    out[2 * t + 1] = make_double4(v[4], v[5], 0.0, 0.0);
+    float r[6];
+    bool safe = true;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int f = e == 2 ? 0 : e + 1;
+        const double ex = v[2 * f] - v[2 * e], ey = v[2 * f + 1] - v[2 * e + 1];
+        safe = safe && ex * ex + ey * ey >= h * h;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double d = v[k] - ((k & 1) ? g.y0 : g.x0);
+        safe = safe && fabs(d) <= m;          // false for NaN and infinities too
+        r[k] = safe ? (float)d : 0.0f;
+    }
+    out32[2 * t] = make_float4(r[0], r[1], r[2], r[3]);
+    out32[2 * t + 1] = make_float4(r[4], r[5], safe ? 1.0f : 0.0f, 0.0f);
 }
 
 // Whether (x, y) is within sqrt(h2) of triangle t: the squared distance
@@ -418,22 +446,58 @@ __device__ inline int particle_cell(const GridDev &g, double x, double y) {
 // Pairs per particle.  A particle whose cell lists at most 64 triangles also
 // keeps the bit mask of those that pass, so that pair_fill need not test them
 // again.
+// The squared distance from (x, y) to a triangle in FP32 (0 inside), the
+// same steps as near_tri with the reciprocal estimate for the quotient.
+__device__ inline float dist2_tri32(float x, float y, const float4 *__restrict__ tv32, int t, bool &safe) {
+    const float4 va = tv32[2 * t], vb = tv32[2 * t + 1];
+    safe = vb.z != 0.0f;
+    const float x0 = va.x, y0 = va.y, x1 = va.z, y1 = va.w, x2 = vb.x, y2 = vb.y;
+    const float c0 = (x1 - x0) * (y - y0) - (y1 - y0) * (x - x0);
+    const float c1 = (x2 - x1) * (y - y1) - (y2 - y1) * (x - x1);
+    const float c2 = (x0 - x2) * (y - y2) - (y0 - y2) * (x - x2);
+    if ((c0 >= 0.0f && c1 >= 0.0f && c2 >= 0.0f) || (c0 <= 0.0f && c1 <= 0.0f && c2 <= 0.0f)) return 0.0f;
+    float best = INFINITY;
+    const float ex[3] = {x0, x1, x2}, ey[3] = {y0, y1, y2};
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const float ax = ex[e], ay = ey[e], ux = ex[(e + 1) % 3], uy = ey[(e + 1) % 3];
+        const float dx = ux - ax, dy = uy - ay;
+        const float L = dx * dx + dy * dy;
+        float sp = L > 0.0f ? ((x - ax) * dx + (y - ay) * dy) * __builtin_amdgcn_rcpf(L) : 0.0f;
+        sp = fminf(fmaxf(sp, 0.0f), 1.0f);
+        const float qx = ax + sp * dx - x, qy = ay + sp * dy - y;
+        best = fminf(best, qx * qx + qy * qy);
+    }
+    return best;
+}
+
+// Pairs per particle.  A candidate is decided by its FP32 distance when that
+// is below lo2 or above hi2 (the support radius less or plus the FP32 error
+// bound, squared); the FP64 test decides the others and the triangles far
+// from the grid.  A particle whose cell lists at most 64 triangles also keeps
+// the bit mask of those that pass, so that pair_fill need not test them again.
 __global__ void pair_count(GridDev g, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
-                           const double4 *__restrict__ tv, double h2, const int *__restrict__ cell_start,
-                           const int *__restrict__ items, int64_t n_refs, int64_t *__restrict__ counts,
-                           uint64_t *__restrict__ mask) {
+                           const double4 *__restrict__ tv, const float4 *__restrict__ tv32, double h2, float lo2,
+                           float hi2, const int *__restrict__ cell_start, const int *__restrict__ items,
+                           int64_t n_refs, int64_t *__restrict__ counts, uint64_t *__restrict__ mask) {
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const double x = px[i], y = py[i];
+    const float xr = (float)(x - g.x0), yr = (float)(y - g.y0);
     const int c = particle_cell(g, x, y);
     const int k0 = cell_start[c], k1 = (int)min((int64_t)cell_start[c + 1], n_refs);
     int64_t n = 0;
     uint64_t m = 0;
-    for (int k = k0; k < k1; ++k)
-        if (near_tri(x, y, tv, items[k], h2)) {
+    for (int k = k0; k < k1; ++k) {
+        const int t = items[k];
+        bool safe;
+        const float d2 = dist2_tri32(xr, yr, tv32, t, safe);
+        const bool pass = safe && d2 < lo2 ? true : (safe && d2 > hi2 ? false : near_tri(x, y, tv, t, h2));
+        if (pass) {
             ++n;
             m |= (uint64_t)1 << ((k - k0) & 63);
         }
+    }
     counts[i] = n;
     mask[i] = m;
 }
@@ -462,7 +526,7 @@ __global__ void pair_fill(GridDev g, int64_t N, const double *__restrict__ px, c
 }
 
 struct WsLayout {
-    size_t cell_start, cursor, items, tri4, mask, scan_tmp, scan_tmp_bytes, total;
+    size_t cell_start, cursor, items, tri4, tri32, mask, scan_tmp, scan_tmp_bytes, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -479,6 +543,7 @@ static int layout(const sphbi_grid *g, int64_t N, int64_t T, WsLayout *L) {
     L->cursor = o; o = align256(o + (ncell + 1) * sizeof(int));
     L->items = o; o = align256(o + (size_t)(g->n_refs > 0 ? g->n_refs : 1) * sizeof(int));
     L->tri4 = o; o = align256(o + (size_t)(T > 0 ? T : 1) * 8 * sizeof(double));
+    L->tri32 = o; o = align256(o + (size_t)(T > 0 ? T : 1) * 8 * sizeof(float));
     L->mask = o; o = align256(o + (size_t)(N > 0 ? N : 1) * sizeof(uint64_t));
     L->scan_tmp = o;
     L->scan_tmp_bytes = t1 > t2 ? t1 : t2;
@@ -572,6 +637,28 @@ int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t 
     char *w = (char *)ws;
     int *cell_start = (int *)(w + L.cell_start), *cursor = (int *)(w + L.cursor), *items = (int *)(w + L.items);
     double4 *tri4 = (double4 *)(w + L.tri4);
+    // FP32 pre-test: coordinates relative to the grid origin within +-m_fp32
+    // (twice the grid's extent), each rounded with error <= m 2^-24 =: eta/2.
+    // The foot point of a segment is then off by at most about 12 eta/2 per
+    // component (the differences, the projection with its 1-ulp reciprocal,
+    // the product and the sums; an error in the projection parameter moves
+    // the foot along the segment, which changes the distance only to second
+    // order), and for a point within h of a triangle whose edges are all at
+    // least h long the FP32 inside test errs only for points within 6 eta of
+    // an edge line.  So the FP32 distance is within e = 32 m 2^-24 + 4 h 2^-24
+    // of the exact one (a generous bound).  Below (h - e)^2 a candidate
+    // passes, above (h + e)^2 it fails, in between the FP64 test decides; the
+    // squares are rounded outwards.  Beyond m = 2^20 h the second-order term
+    // is no longer small and every candidate takes the FP64 test.
+    const double m_fp32 = 2.0 * (double)(grid->nx > grid->ny ? grid->nx : grid->ny) * grid->cell + 2.0 * h;
+    const double e_fp32 = (32.0 * m_fp32 + 4.0 * h) * 0x1p-24;
+    const double lo = h - e_fp32 > 0.0 ? h - e_fp32 : 0.0;
+    float lo2 = nextafterf((float)(lo * lo * (1.0 - 0x1p-20)), 0.0f);
+    float hi2 = nextafterf((float)((h + e_fp32) * (h + e_fp32) * (1.0 + 0x1p-20)), INFINITY);
+    if (!(m_fp32 <= 0x1p20 * h)) {
+        lo2 = 0.0f;
+        hi2 = INFINITY;
+    }
     const size_t ncell = (size_t)grid->nx * grid->ny;
     GridDev g = to_dev(grid);
     // 16 lanes per triangle, grid-stride beyond 2^16 blocks
@@ -579,7 +666,8 @@ int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t 
     const unsigned ref_blocks = (unsigned)(rb < 65536 ? (rb > 0 ? rb : 1) : 65536);
     CHECK_HIP(hipMemsetAsync(cursor, 0, (ncell + 1) * sizeof(int), s));
     if (T > 0) {
-        hipLaunchKernelGGL(tri_pack, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, T, tri, tri4);
+        hipLaunchKernelGGL(tri_pack, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, m_fp32, h, T, tri, tri4,
+                           (float4 *)(w + L.tri32));
         hipLaunchKernelGGL(tri_ref_cells<false>, dim3(ref_blocks), dim3(256), 0, s, g, T, tri, h, cursor,
                            (const int *)nullptr, (int *)nullptr, (int64_t)0);
     }
@@ -598,7 +686,8 @@ int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t 
     CHECK_HIP(hipMemsetAsync(offsets, 0, sizeof(int64_t), s));
     if (N > 0) {
         hipLaunchKernelGGL(pair_count, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g, N, px, py,
-                           (const double4 *)tri4, h * h, cell_start, items, grid->n_refs, offsets + 1,
+                           (const double4 *)tri4, (const float4 *)(w + L.tri32), h * h, lo2, hi2, cell_start, items,
+                           grid->n_refs, offsets + 1,
                            (uint64_t *)(w + L.mask));
         CHECK_HIP(hipGetLastError());
         tb = L.scan_tmp_bytes;

@@ -104,6 +104,39 @@ def test_pairlist_crowded_cells():
     assert np.array_equal(off2.cpu().numpy(), off) and np.array_equal(idx2.cpu().numpy(), idx)
 
 
+def test_pairlist_particles_at_the_support_radius():
+    """Particles placed 1e-2..1e-9 h inside and outside the support radius of
+    triangles whose edges are longer than h (the ones the count pass first
+    tests in FP32): the same pairs as the brute-force oracle."""
+    say("pairlist at the support radius")
+    rng = np.random.default_rng(12)
+    h = 0.01
+    T = 400
+    c = rng.uniform(0.1, 0.9, size=(2, T))
+    tri = np.empty((6, T))
+    for v in range(3):
+        ang = 2 * np.pi * v / 3 + rng.uniform(-0.3, 0.3, T)
+        tri[2 * v] = c[0] + 3 * h * np.cos(ang)
+        tri[2 * v + 1] = c[1] + 3 * h * np.sin(ang)
+    px, py = [], []
+    for t in range(T):
+        v = tri[:, t].reshape(3, 2)
+        e = rng.integers(3)
+        a, b = v[e], v[(e + 1) % 3]
+        f = a + rng.uniform(0.1, 0.9) * (b - a)              # a point on the edge
+        nrm = np.array([b[1] - a[1], a[0] - b[0]]) / np.hypot(*(b - a))
+        if np.dot(nrm, f - v.mean(0)) < 0:
+            nrm = -nrm                                        # outward
+        for d in (1e-2, 1e-5, 1e-7, 1e-9):
+            for sgn in (-1.0, 1.0):
+                q = f + nrm * h * (1.0 + sgn * d)
+                px.append(q[0])
+                py.append(q[1])
+    wl = W.Workload("support_radius", np.array(px), np.array(py), tri, np.ones((1, T)), h, 0, meta={})
+    off, idx, diff = check_pairlist(wl)
+    say(f"  {off[-1]} pairs, {diff} ties at the radius")
+
+
 def test_pairlist_edge_cases():
     say("pairlist edge cases")
     # no particles, no triangles, all far away
