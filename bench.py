@@ -16,7 +16,8 @@ own closed form, counted by the instrumented closed-form oracle on a sample of
 the workload's pairs.  The JSON line also carries the dominant kernel's roofline
 position, the CPU oracle timed on a bounded sample and, under "modes":
 the same step in the mixed FP32/FP64 precision mode with its largest
-scale-normalised deviation from the FP64 results; the SPH operators; the
+scale-normalised deviation from the FP64 results; the precision-stress table
+and the cost of the default refinement on ordinary meshes; the SPH operators; the
 quadrature comparison (collapsed Gauss-Legendre rules of 4..32 points per
 direction, time and error against the closed form); the adjoint on the
 differentiation workload (262,144 particles, Wendland C4, P3); and the
@@ -191,6 +192,47 @@ def bench_precision_stress(args, sb, W, torch, dev):
     out["workload"] = ("262,144 particles, 16,384 slivers (min angle 0.5 deg), h = 1/512, cubic N(0,1) fields; "
                        "errors per particle, scale-normalised, against the all-double-double evaluation (itself "
                        "within 1e-15 of the oracle: tests/test_gpu_forward.py)")
+    return out
+
+
+def bench_refinement_cost(args, sb, W, torch, dev):
+    """What the default conditioning gate costs on ordinary meshes: 512^2
+    jittered particles over a 64 x 128 covering mesh (aspect ratio up to 20,
+    1.45M pairs), per kernel and field order: the fraction of pairs refined,
+    the call with refinement off and the default call (warm, HIP events), and
+    the largest scale-normalised per-particle difference of the refinement-off
+    call from the all-double-double one."""
+    out = {}
+    cases = (("wendland_c4_p3", 1, 3, 4), ("wendland_c6_p3", 2, 3, 5), ("wendland_c6_p1", 2, 1, 5),
+             ("cubic_bspline_p3", 3, 3, 5))
+    for name, kid, order, seed in cases:
+        wl = W.covering_workload(n_side=512, nx=64, ny=128, seed=seed, kernel=kid, field_order=order)
+        t = [torch.tensor(a, device=dev) for a in (wl.px, wl.py, wl.tri, wl.nodal)]
+        off, idx = sb.pairlist(t[0], t[1], t[2], wl.h)
+        P = int(idx.numel())
+        auto = sb.integrate(kid, wl.h, *t, off, idx, per_pair=True)
+        plain = sb.integrate(kid, wl.h, *t, off, idx, per_pair=True, refine=sb.REFINE_OFF)
+        dd = sb.integrate(kid, wl.h, *t, off, idx, refine=sb.REFINE_ALL)
+        refined = int(torch.any(auto[3] != plain[3], dim=0).sum())
+        amax = float(np.abs(wl.nodal).max()) * (3.0 if order == 3 else 1.0)
+        sG = 2 * kernel_c_d_int_k(sb, kid) / wl.h * amax
+        e_off = max(float((torch.abs(plain[0] - dd[0]) / torch.clamp(torch.abs(dd[0]), min=amax)).max()),
+                    max(float((torch.abs(plain[k] - dd[k]) / torch.clamp(torch.abs(dd[k]), min=sG)).max())
+                        for k in (1, 2)))
+        e_auto = max(float((torch.abs(auto[0] - dd[0]) / torch.clamp(torch.abs(dd[0]), min=amax)).max()),
+                     max(float((torch.abs(auto[k] - dd[k]) / torch.clamp(torch.abs(dd[k]), min=sG)).max())
+                         for k in (1, 2)))
+        integ_off = sb.Integrator(kid, wl.h, wl.n_nodes, refine=sb.REFINE_OFF)
+        integ = sb.Integrator(kid, wl.h, wl.n_nodes)
+        ms_off = event_time(torch, lambda: integ_off(*t, off, idx), 10, 3)
+        ms_auto = event_time(torch, lambda: integ(*t, off, idx), 10, 3)
+        out[name] = {"pairs": P, "refined": refined, "refined_fraction": refined / P, "ms_refinement_off": ms_off,
+                     "ms_default": ms_auto, "max_scaled_err_refinement_off": e_off, "max_scaled_err_default": e_auto}
+        log(f"bench: refinement cost {name}: {refined} of {P} pairs refined, {ms_off:.3f} -> {ms_auto:.3f} ms; "
+            f"error off {e_off:.1e}, default {e_auto:.1e}")
+    out["workload"] = ("262,144 particles (jittered 512^2 grid) over a 64 x 128 covering mesh (16,384 triangles, "
+                       "aspect ratio up to 20); errors per particle, scale-normalised, against the all-double-double "
+                       "evaluation")
     return out
 
 
@@ -666,6 +708,7 @@ def main():
 
     if not args.no_precision_stress:
         result["modes"]["precision_stress"] = bench_precision_stress(args, sb, W, torch, dev)
+        result["modes"]["refinement_cost"] = bench_refinement_cost(args, sb, W, torch, dev)
     if not args.no_operators:
         result["modes"]["operators"] = bench_operators(args, sb, torch, dev, wl, px, py, tri, nodal, off, idx,
                                                        kern_avg)

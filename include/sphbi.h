@@ -106,8 +106,8 @@ typedef struct {
     double tau_edge;    /* MIXED: pairs whose particle lies within tau_edge*h of an
                            edge line or vertex are evaluated in FP64 (default 1e-4) */
     double refine_gate; /* threshold on Kf kappa^order; 0 = the default,
-                           G0 (141/Kf)^1.25 with G0 = 3e6 for cubic and 3e7 for
-                           linear fields (FP64), 1e9 (MIXED) */
+                           FP64: G0 (141/Kf)^1.65 with G0 = 3e6 for cubic and 3e8
+                           for linear fields; MIXED: 1e9 (141/Kf)^1.25 */
     uint8_t *pair_status; /* optional DEVICE array [n_pairs] (sphbi_integrate, _noalloc,
                              _prepared): per pair 1 if any of its three results is not
                              finite (NaN or Inf from degenerate or non-finite input), else 0;

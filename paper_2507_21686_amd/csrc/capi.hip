@@ -805,19 +805,24 @@ int sphbi_integrate_prepared(const sphbi_kernel *kernel, const sphbi_opts *opts,
 namespace sphbi {
 
 // Default thresholds of the conditioning gate on Kf kappa^order (see
-// sphbi_opts), G = G0 (141 / Kf)^1.25, 141 being Kf of Wendland C2.  Fitted
-// to the per-pair errors measured against the double-double path on
-// covering meshes (aspect ratio 20 and 60, cubic and linear fields) and on
-// 0.5-degree slivers with particles 1e-8..1e-2 h from edges and vertices.
-// With G0 = 3e6 for cubic fields the FP64 pass stays within 1e-12 of the
-// scale for Wendland C2, C4 and C6 (the Wendland C2 covering mesh of 2^20
-// particles has no pair above it).  Linear fields lose less (kappa^1): with
-// G0 = 3e7 every preset kernel stays within 1e-12 on those workloads (largest
-// kept error 5.2e-13, Wendland C6 on a covering mesh, where 3e6 sent two
-// thirds of the pairs to double-double for errors already below 6e-13),
-// while the C6 slivers are still all refined.  With G0 = 1e9 the mixed pass
-// stays within 1e-6.
-constexpr double kGateFP64 = 3e6, kGateFP64Linear = 3e7, kGateMixed = 1e9;
+// sphbi_opts), G = G0 (141 / Kf)^a, 141 being Kf of Wendland C2.  Fitted to
+// the errors measured against the double-double path, per pair and per
+// particle, on covering meshes (512^2 particles, aspect ratio 20 and 60,
+// cubic and linear fields, three seeds) and on 0.5-degree slivers with
+// particles 1e-8..1e-2 h from edges and vertices:
+//  * FP64, cubic fields: G0 = 3e6, a = 1.65.  Wendland C2 keeps the headline
+//    mesh of 2^20 particles unrefined (largest Kf kappa^3 2.2e6, error
+//    4.8e-13); Wendland C4 needs G <= 1e5 to stay within 1e-12 per particle
+//    (with 2.3e5 the sums of ~5.5 pairs each within 8.5e-13 reached
+//    1.0-1.3e-12); C6 and the slivers are refined almost wholly either way.
+//  * FP64, linear fields (they lose kappa^1, not kappa^3): G0 = 3e8, the same
+//    a; every preset kernel stays within 1e-12 (largest kept error 6.2e-13,
+//    Wendland C6 on a covering mesh, where the cubic fields' threshold sent
+//    two thirds of the pairs to double-double) while the C6 slivers are
+//    still all refined.
+//  * Mixed: G0 = 1e9, a = 1.25, which holds the 1e-6 target.
+constexpr double kGateFP64 = 3e6, kGateFP64Linear = 3e8, kGateMixed = 1e9;
+constexpr double kGateExpFP64 = 1.65, kGateExpMixed = 1.25;
 
 // Kf = sum_p sum_k |b_pk| R_p^(k+2)/(k+2) / |sum_p sum_k b_pk R_p^(k+2)/(k+2)|:
 // the cancellation of the kernel's monomial form in the integral over the
@@ -836,11 +841,10 @@ static double kernel_cancellation(const KArgs &K) {
 RefineGate make_gate(const sphbi_opts &o, int order, const KArgs &K) {
     if (o.refine != SPHBI_REFINE_AUTO || order == 0) return refine_off();
     const double kf = kernel_cancellation(K);
+    const bool mixed = o.precision == SPHBI_MIXED;
+    const double g0 = mixed ? kGateMixed : (order == 1 ? kGateFP64Linear : kGateFP64);
     const double thr = o.refine_gate > 0.0 ? o.refine_gate
-                                           : (o.precision == SPHBI_MIXED ? kGateMixed
-                                              : order == 1                   ? kGateFP64Linear
-                                                                             : kGateFP64) *
-                                                 pow(141.0 / kf, 1.25);
+                                           : g0 * pow(141.0 / kf, mixed ? kGateExpMixed : kGateExpFP64);
     if (!isfinite(thr)) return refine_off();
     const double g = thr / kf;
     return RefineGate{order, 0, g * g};
