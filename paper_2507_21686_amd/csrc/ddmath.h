@@ -15,9 +15,14 @@
 //
 // The error-free transformations are Knuth's TwoSum, Dekker's FastTwoSum and
 // the fused-multiply-add form of TwoProduct; the compound operations follow
-// the usual double-double algorithms (accurate addition with two TwoSums,
-// multiplication with the cross terms, division by two correction steps,
-// square root by one Newton step).  They rely on every product and sum being
+// the usual double-double algorithms (addition with one TwoSum of the high
+// parts, multiplication with the cross terms, division by two correction
+// steps, square root by one Newton step).  The addition is the short form:
+// its error is a few units of 2^-106 of |a| + |b| rather than of the sum, so a
+// single addition that cancels by a factor F keeps about 32 - log10(F)
+// digits -- the same budget as the conditioning above, and well inside it
+// (the longer form, a second TwoSum of the low parts, cost a sixth more time
+// in the refinement pass and changed no result by more than 1e-22).  They rely on every product and sum being
 // rounded on its own exactly as written: a product fused into a following
 // addition (FP contraction, on by default for device code) breaks the error
 // terms -- measured on gfx950: products and quotients then carry 1e-16
@@ -77,10 +82,7 @@ __host__ __device__ inline dd operator-(const dd &a) {
 __host__ __device__ inline dd operator+(const dd &a, const dd &b) {
     SPHBI_DD_EXACT
     dd s = two_sum(a.hi, b.hi);
-    const dd t = two_sum(a.lo, b.lo);
-    s.lo += t.hi;
-    s = fast_two_sum(s.hi, s.lo);
-    s.lo += t.lo;
+    s.lo += a.lo + b.lo;
     return fast_two_sum(s.hi, s.lo);
 }
 __host__ __device__ inline dd operator+(const dd &a, double b) {
