@@ -107,16 +107,18 @@ __host__ __device__ inline dd operator-(double a, const dd &b) {
     SPHBI_DD_EXACT
     return (-b) + a;
 }
+// (the cross terms are folded into the error term with explicit fused
+// multiply-adds: one rounding each instead of two)
 __host__ __device__ inline dd operator*(const dd &a, const dd &b) {
     SPHBI_DD_EXACT
     dd p = two_prod(a.hi, b.hi);
-    p.lo += a.hi * b.lo + a.lo * b.hi;
+    p.lo = fma(a.hi, b.lo, fma(a.lo, b.hi, p.lo));
     return fast_two_sum(p.hi, p.lo);
 }
 __host__ __device__ inline dd operator*(const dd &a, double b) {
     SPHBI_DD_EXACT
     dd p = two_prod(a.hi, b);
-    p.lo += a.lo * b;
+    p.lo = fma(a.lo, b, p.lo);
     return fast_two_sum(p.hi, p.lo);
 }
 __host__ __device__ inline dd operator*(double a, const dd &b) {
