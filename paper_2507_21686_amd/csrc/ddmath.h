@@ -112,13 +112,13 @@ __host__ __device__ inline dd operator-(double a, const dd &b) {
 __host__ __device__ inline dd operator*(const dd &a, const dd &b) {
     SPHBI_DD_EXACT
     dd p = two_prod(a.hi, b.hi);
-    p.lo = fma(a.hi, b.lo, fma(a.lo, b.hi, p.lo));
+    p.lo = ::fma(a.hi, b.lo, ::fma(a.lo, b.hi, p.lo));
     return fast_two_sum(p.hi, p.lo);
 }
 __host__ __device__ inline dd operator*(const dd &a, double b) {
     SPHBI_DD_EXACT
     dd p = two_prod(a.hi, b);
-    p.lo = fma(a.lo, b, p.lo);
+    p.lo = ::fma(a.lo, b, p.lo);
     return fast_two_sum(p.hi, p.lo);
 }
 __host__ __device__ inline dd operator*(double a, const dd &b) {
@@ -213,17 +213,28 @@ __host__ __device__ inline dd copysign(const dd &a, const dd &s) {
     SPHBI_DD_EXACT
     return (s.hi < 0.0) != (a.hi < 0.0) ? -a : a;
 }
+// a b + c with the product left unnormalised: (p, e) goes straight into the
+// addition, which only needs |e| small beside p (the error is that of the
+// addition, a few units of 2^-106 of |a b| + |c|)
 __host__ __device__ inline dd fma(const dd &a, const dd &b, const dd &c) {
     SPHBI_DD_EXACT
-    return a * b + c;
+    const dd p = two_prod(a.hi, b.hi);
+    const double e = ::fma(a.hi, b.lo, ::fma(a.lo, b.hi, p.lo));
+    dd s = two_sum(p.hi, c.hi);
+    s.lo += e + c.lo;
+    return fast_two_sum(s.hi, s.lo);
 }
 __host__ __device__ inline dd fma(double a, const dd &b, const dd &c) {
     SPHBI_DD_EXACT
-    return b * a + c;
+    const dd p = two_prod(a, b.hi);
+    const double e = ::fma(a, b.lo, p.lo);
+    dd s = two_sum(p.hi, c.hi);
+    s.lo += e + c.lo;
+    return fast_two_sum(s.hi, s.lo);
 }
 __host__ __device__ inline dd fma(const dd &a, double b, const dd &c) {
     SPHBI_DD_EXACT
-    return a * b + c;
+    return fma(b, a, c);
 }
 __host__ __device__ inline dd ldexp(const dd &a, int e) {
     SPHBI_DD_EXACT

@@ -14,5 +14,7 @@ void t_sqrt(double h, double l, double *o) { const dd r = sphbi::dd_sqrt(dd(h, l
 void t_div(double ah, double al, double bh, double bl, double *o) { const dd r = dd(ah, al) / dd(bh, bl); o[0] = r.hi; o[1] = r.lo; }
 void t_mul(double ah, double al, double bh, double bl, double *o) { const dd r = dd(ah, al) * dd(bh, bl); o[0] = r.hi; o[1] = r.lo; }
 void t_add(double ah, double al, double bh, double bl, double *o) { const dd r = dd(ah, al) + dd(bh, bl); o[0] = r.hi; o[1] = r.lo; }
+void t_fma(double ah, double al, double bh, double bl, double ch, double cl, double *o) { const dd r = fma(dd(ah, al), dd(bh, bl), dd(ch, cl)); o[0] = r.hi; o[1] = r.lo; }
+void t_fma1(double a, double bh, double bl, double ch, double cl, double *o) { const dd r = fma(a, dd(bh, bl), dd(ch, cl)); o[0] = r.hi; o[1] = r.lo; }
 void t_recip(int n, double *o) { const dd r = sphbi::dd_recip(n); o[0] = r.hi; o[1] = r.lo; }
 }

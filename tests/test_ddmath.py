@@ -33,6 +33,8 @@ def ddlib():
     for f in (L.t_atan2, L.t_div, L.t_mul, L.t_add):
         f.argtypes = [d, d, d, d, C.c_void_p]
     L.t_recip.argtypes = [C.c_int, C.c_void_p]
+    L.t_fma.argtypes = [d, d, d, d, d, d, C.c_void_p]
+    L.t_fma1.argtypes = [d, d, d, d, d, C.c_void_p]
     return L
 
 
@@ -63,6 +65,15 @@ def test_ddmath_against_mpmath(ddlib):
         ddlib.t_mul(a, al, b, bl, P); rec("mul", _val(out), A * B)
         ddlib.t_add(a, al, b, bl, P)
         worst["add"] = max(worst.get("add", 0.0), float(abs(_val(out) - (A + B)) / (abs(A) + abs(B))))
+        # fused a b + c, the product unnormalised: within the addition's bound of |a b| + |c|
+        c = -a * b * float(rng.uniform(0.9, 1.1))
+        cl = c * 1e-17 * rng.uniform(-1, 1)
+        Cc = mp.mpf(c) + mp.mpf(cl)
+        ddlib.t_fma(a, al, b, bl, c, cl, P)
+        worst["fma"] = max(worst.get("fma", 0.0), float(abs(_val(out) - (A * B + Cc)) / (abs(A * B) + abs(Cc))))
+        ddlib.t_fma1(b, a, al, c, cl, P)
+        worst["fma1"] = max(worst.get("fma1", 0.0),
+                            float(abs(_val(out) - (mp.mpf(b) * A + Cc)) / (abs(mp.mpf(b) * A) + abs(Cc))))
         # exact cancellation of the high parts: the low parts' sum, to the bound
         ddlib.t_add(a, al, -a, -al * 0.5, P)
         assert abs(_val(out) - (A - mp.mpf(a) - mp.mpf(al * 0.5))) <= mp.mpf(2) ** -103 * (2 * abs(A))
