@@ -61,6 +61,7 @@ extern "C" {
 #define SPHBI_EDEVICE -3      /* HIP launch or runtime error */
 #define SPHBI_ENOWORKSPACE -4 /* workspace missing or too small */
 #define SPHBI_ECAPACITY -5    /* output capacity too small (count returned) */
+#define SPHBI_EGRID -6        /* a particle lies outside the grid being reused: plan again */
 
 #define SPHBI_WENDLAND_C2 0
 #define SPHBI_WENDLAND_C4 1
@@ -134,11 +135,24 @@ const char *sphbi_last_error(void);
  *
  * sphbi_pairlist_plan: sizes the uniform cell grid (cell >= h) over the
  * particles' bounding box and returns the workspace the two later calls need.
+ * A particle coordinate that is not finite returns SPHBI_EINVAL.
  * Synchronises `stream`.
  *
  * sphbi_pairlist_count: builds the grid in `ws`, counts the pairs of every
  * particle and writes offsets[0..N]; *n_pairs (host) receives offsets[N].
  * Synchronises `stream`.
+ *
+ * sphbi_pairlist_recount: sphbi_pairlist_count for new particle positions on
+ * a grid and cell lists built before, for a mesh that has not moved (same
+ * tri, T and h as the count call that built `ws`, which must not have been
+ * overwritten since).  N may differ from that call's; ws_bytes must then
+ * still cover the layout sphbi_pairlist_plan would give for the new N on
+ * this grid (it does whenever N did not grow).  Skips the cell lists' build
+ * (about a third of the three calls' time on a million particles).  If any
+ * particle lies outside the grid's nx x ny cells, or has a non-finite
+ * coordinate, the offsets written are incomplete and the call returns
+ * SPHBI_EGRID: plan and count again.  The result is identical to a fresh
+ * plan + count on the same grid.  Synchronises `stream`.
  *
  * sphbi_pairlist_fill: writes tri_idx[0 .. n_pairs-1] using the offsets and
  * the grid, cell lists and per-particle candidate masks left in `ws` by the
@@ -158,6 +172,9 @@ int sphbi_pairlist_plan(int64_t N, const double *px, const double *py, int64_t T
 int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t T, const double *tri,
                          double h, const sphbi_grid *grid /* host */, void *ws, size_t ws_bytes,
                          int64_t *offsets, int64_t *n_pairs /* host out */, void *stream);
+int sphbi_pairlist_recount(int64_t N, const double *px, const double *py, int64_t T, const double *tri,
+                           double h, const sphbi_grid *grid /* host */, void *ws, size_t ws_bytes,
+                           int64_t *offsets, int64_t *n_pairs /* host out */, void *stream);
 int sphbi_pairlist_fill(int64_t N, const double *px, const double *py, int64_t T, const double *tri,
                         double h, const sphbi_grid *grid /* host */, void *ws, size_t ws_bytes,
                         const int64_t *offsets, int32_t *tri_idx, int64_t cap, void *stream);

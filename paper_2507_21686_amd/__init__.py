@@ -20,10 +20,11 @@ LIB_PATH = os.path.join(HERE, "libsphbi.so")
 WENDLAND_C2, WENDLAND_C4, WENDLAND_C6, CUBIC_BSPLINE = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 REFINE_AUTO, REFINE_OFF, REFINE_ALL = 0, 1, 2
-STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENOWORKSPACE", -5: "ECAPACITY"}
+STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "EDEVICE", -4: "ENOWORKSPACE", -5: "ECAPACITY", -6: "EGRID"}
+EGRID = -6
 
 EXPORTS = ["sphbi_kernel_preset", "sphbi_default_opts", "sphbi_last_error", "sphbi_pairlist_plan",
-           "sphbi_pairlist_count", "sphbi_pairlist_fill", "sphbi_integrate_workspace", "sphbi_integrate",
+           "sphbi_pairlist_count", "sphbi_pairlist_recount", "sphbi_pairlist_fill", "sphbi_integrate_workspace", "sphbi_integrate",
            "sphbi_field_prepare", "sphbi_integrate_prepared", "sphbi_integrate_backward_workspace",
            "sphbi_integrate_backward", "sphbi_surrogate_features", "sphbi_surrogate_targets", "sphbi_mlp_workspace", "sphbi_mlp_forward",
            "sphbi_mlp_loss_grad", "sphbi_adam_step", "sphbi_surrogate_model_bytes", "sphbi_surrogate_pack",
@@ -70,6 +71,7 @@ def lib():
         L.sphbi_pairlist_plan.argtypes = [i64, vp, vp, i64, vp, d, C.POINTER(SphbiGrid), C.POINTER(C.c_size_t), vp]
         L.sphbi_pairlist_count.argtypes = [i64, vp, vp, i64, vp, d, C.POINTER(SphbiGrid), vp, C.c_size_t, vp,
                                            C.POINTER(C.c_int64), vp]
+        L.sphbi_pairlist_recount.argtypes = L.sphbi_pairlist_count.argtypes
         L.sphbi_pairlist_fill.argtypes = [i64, vp, vp, i64, vp, d, C.POINTER(SphbiGrid), vp, C.c_size_t, vp, vp,
                                           i64, vp]
         L.sphbi_integrate_workspace.argtypes = [i64]
@@ -168,6 +170,75 @@ def pairlist(px, py, tri, h: float):
     _check(L.sphbi_pairlist_fill(N, _ptr(px), _ptr(py), T, _ptr(tri), float(h), C.byref(grid), _ptr(ws), ws.numel(),
                                  _ptr(offsets), _ptr(tri_idx), int(n.value), s), "sphbi_pairlist_fill")
     return offsets, tri_idx[: int(n.value)]
+
+
+class PairList:
+    """Pair lists of a mesh that does not move, for particles that do.
+
+    Keeps the cell grid and its triangle lists between calls and only counts
+    and fills the pairs again (``sphbi_pairlist_recount``); the grid is
+    planned again, over the particles' bounding box grown by ``pad`` on every
+    side, when a particle has left it or N has grown.  ``tri`` must not change
+    while the object is in use.  The lists are identical to ``pairlist``'s
+    (the pair tests do not depend on the grid).
+    """
+
+    def __init__(self, tri, h: float, pad: float | None = None):
+        self.tri = _dev(tri)
+        self.h = float(h)
+        self.pad = 2.0 * self.h if pad is None else float(pad)
+        self.grid = None
+        self.ws = None
+        self.n_plan = 0       # particles the workspace was sized for
+        self.plans = self.reuses = 0
+
+    def _plan_on(self, px, py):
+        grid, ws_bytes = SphbiGrid(), C.c_size_t(0)
+        _check(lib().sphbi_pairlist_plan(px.numel(), _ptr(px), _ptr(py), self.tri.shape[1], _ptr(self.tri), self.h,
+                                         C.byref(grid), C.byref(ws_bytes), _stream()), "sphbi_pairlist_plan")
+        return grid, ws_bytes
+
+    def _plan(self, px, py):
+        grid, ws_bytes = self._plan_on(px, py)
+        if self.pad > 0.0 and px.numel() > 0:
+            # plan again with two corner points that grow the particles' box
+            # (x0, y0 is its low corner, the cells reach past its high one)
+            g = grid
+            cx = torch.tensor([g.x0 - self.pad, g.x0 + g.nx * g.cell + self.pad], dtype=torch.float64)
+            cy = torch.tensor([g.y0 - self.pad, g.y0 + g.ny * g.cell + self.pad], dtype=torch.float64)
+            qx = torch.cat([px, cx.to(px.device)])
+            qy = torch.cat([py, cy.to(py.device)])
+            grid, ws_bytes = self._plan_on(qx, qy)
+        self.grid = grid
+        self.ws = torch.empty(max(int(ws_bytes.value), 1), dtype=torch.uint8, device=px.device)
+        self.n_plan = px.numel()
+        self.plans += 1
+
+    def __call__(self, px, py):
+        """(offsets int64 [N+1], tri_idx int32 [P]) for the current positions."""
+        px, py = _dev(px), _dev(py)
+        N, T = px.numel(), self.tri.shape[1]
+        L, s = lib(), _stream()
+        offsets = torch.empty(N + 1, dtype=torch.int64, device=px.device)
+        n = C.c_int64(0)
+        rc = EGRID
+        if self.grid is not None and N <= self.n_plan:
+            rc = L.sphbi_pairlist_recount(N, _ptr(px), _ptr(py), T, _ptr(self.tri), self.h, C.byref(self.grid),
+                                          _ptr(self.ws), self.ws.numel(), _ptr(offsets), C.byref(n), s)
+            if rc == 0:
+                self.reuses += 1
+            elif rc != EGRID:
+                _check(rc, "sphbi_pairlist_recount")
+        if rc == EGRID:
+            self._plan(px, py)
+            _check(L.sphbi_pairlist_count(N, _ptr(px), _ptr(py), T, _ptr(self.tri), self.h, C.byref(self.grid),
+                                          _ptr(self.ws), self.ws.numel(), _ptr(offsets), C.byref(n), s),
+                   "sphbi_pairlist_count")
+        tri_idx = torch.empty(max(int(n.value), 1), dtype=torch.int32, device=px.device)
+        _check(L.sphbi_pairlist_fill(N, _ptr(px), _ptr(py), T, _ptr(self.tri), self.h, C.byref(self.grid),
+                                     _ptr(self.ws), self.ws.numel(), _ptr(offsets), _ptr(tri_idx), int(n.value), s),
+               "sphbi_pairlist_fill")
+        return offsets, tri_idx[: int(n.value)]
 
 
 class Integrator:

@@ -162,8 +162,10 @@ __global__ void bbox_partial(int64_t N, const double *__restrict__ px, const dou
     double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
         const double x = px[i], y = py[i];
-        mnx = fmin(mnx, x); mxx = fmax(mxx, x);
-        mny = fmin(mny, y); mxy = fmax(mxy, y);
+        // fmin and fmax drop NaN: count it as -inf in the minima instead,
+        // so that the plan sees a non-finite box
+        mnx = fmin(mnx, x == x ? x : -INFINITY); mxx = fmax(mxx, x);
+        mny = fmin(mny, y == y ? y : -INFINITY); mxy = fmax(mxy, y);
     }
     s[0][threadIdx.x] = mnx; s[1][threadIdx.x] = mny; s[2][threadIdx.x] = mxx; s[3][threadIdx.x] = mxy;
     __syncthreads();
@@ -476,13 +478,23 @@ __device__ inline float dist2_tri32(float x, float y, const float4 *__restrict__
 // bound, squared); the FP64 test decides the others and the triangles far
 // from the grid.  A particle whose cell lists at most 64 triangles also keeps
 // the bit mask of those that pass, so that pair_fill need not test them again.
+//
+// outside (nullable): set when a particle lies outside the grid's cells (or
+// has a non-finite coordinate); its cell is then clamped to the border and
+// pairs with triangles registered only beyond the grid are missed, so a
+// list counted on a grid planned for other positions must be planned again.
 __global__ void pair_count(GridDev g, int64_t N, const double *__restrict__ px, const double *__restrict__ py,
                            const double4 *__restrict__ tv, const float4 *__restrict__ tv32, double h2, float lo2,
                            float hi2, const int *__restrict__ cell_start, const int *__restrict__ items,
-                           int64_t n_refs, int64_t *__restrict__ counts, uint64_t *__restrict__ mask) {
+                           int64_t n_refs, int64_t *__restrict__ counts, uint64_t *__restrict__ mask,
+                           int *__restrict__ outside) {
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const double x = px[i], y = py[i];
+    if (outside) {
+        const double fx = floor((x - g.x0) * g.icell), fy = floor((y - g.y0) * g.icell);
+        if (!(fx >= 0.0 && fx <= g.nx - 1 && fy >= 0.0 && fy <= g.ny - 1)) *outside = 1;
+    }
     const float xr = (float)(x - g.x0), yr = (float)(y - g.y0);
     const int c = particle_cell(g, x, y);
     const int k0 = cell_start[c], k1 = (int)min((int64_t)cell_start[c + 1], n_refs);
@@ -526,7 +538,7 @@ __global__ void pair_fill(GridDev g, int64_t N, const double *__restrict__ px, c
 }
 
 struct WsLayout {
-    size_t cell_start, cursor, items, tri4, tri32, mask, scan_tmp, scan_tmp_bytes, total;
+    size_t cell_start, cursor, items, tri4, tri32, mask, flag, scan_tmp, scan_tmp_bytes, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -545,6 +557,7 @@ static int layout(const sphbi_grid *g, int64_t N, int64_t T, WsLayout *L) {
     L->tri4 = o; o = align256(o + (size_t)(T > 0 ? T : 1) * 8 * sizeof(double));
     L->tri32 = o; o = align256(o + (size_t)(T > 0 ? T : 1) * 8 * sizeof(float));
     L->mask = o; o = align256(o + (size_t)(N > 0 ? N : 1) * sizeof(uint64_t));
+    L->flag = o; o = align256(o + sizeof(int));
     L->scan_tmp = o;
     L->scan_tmp_bytes = t1 > t2 ? t1 : t2;
     o = align256(o + L->scan_tmp_bytes);
@@ -623,9 +636,15 @@ int sphbi_pairlist_plan(int64_t N, const double *px, const double *py, int64_t T
     return SPHBI_OK;
 }
 
-int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t T, const double *tri, double h,
-                         const sphbi_grid *grid, void *ws, size_t ws_bytes, int64_t *offsets, int64_t *n_pairs,
-                         void *stream) {
+}  // extern "C"
+
+namespace sphbi {
+
+// count, and with build_cells the grid's cell lists before it (recount
+// reuses those a count call left in ws)
+static int pairlist_count_impl(int64_t N, const double *px, const double *py, int64_t T, const double *tri, double h,
+                               const sphbi_grid *grid, void *ws, size_t ws_bytes, int64_t *offsets, int64_t *n_pairs,
+                               void *stream, bool build_cells) {
     int rc = check_pairlist_args(N, px, py, T, tri, h);
     if (rc) return rc;
     if (!grid || !n_pairs || !offsets) { set_error("grid/offsets/n_pairs is NULL"); return SPHBI_EINVAL; }
@@ -664,39 +683,67 @@ int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t 
     // 16 lanes per triangle, grid-stride beyond 2^16 blocks
     const int64_t rb = (T * 16 + 255) / 256;
     const unsigned ref_blocks = (unsigned)(rb < 65536 ? (rb > 0 ? rb : 1) : 65536);
-    CHECK_HIP(hipMemsetAsync(cursor, 0, (ncell + 1) * sizeof(int), s));
-    if (T > 0) {
-        hipLaunchKernelGGL(tri_pack, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, m_fp32, h, T, tri, tri4,
-                           (float4 *)(w + L.tri32));
-        hipLaunchKernelGGL(tri_ref_cells<false>, dim3(ref_blocks), dim3(256), 0, s, g, T, tri, h, cursor,
-                           (const int *)nullptr, (int *)nullptr, (int64_t)0);
+    if (build_cells) {
+        CHECK_HIP(hipMemsetAsync(cursor, 0, (ncell + 1) * sizeof(int), s));
+        if (T > 0) {
+            hipLaunchKernelGGL(tri_pack, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g, m_fp32, h, T, tri,
+                               tri4, (float4 *)(w + L.tri32));
+            hipLaunchKernelGGL(tri_ref_cells<false>, dim3(ref_blocks), dim3(256), 0, s, g, T, tri, h, cursor,
+                               (const int *)nullptr, (int *)nullptr, (int64_t)0);
+        }
+        CHECK_HIP(hipGetLastError());
+        size_t tb = L.scan_tmp_bytes;
+        CHECK_HIP(rocprim::exclusive_scan(w + L.scan_tmp, tb, cursor, cell_start, 0, (size_t)(ncell + 1),
+                                          rocprim::plus<int>(), s));
+        CHECK_HIP(hipMemsetAsync(cursor, 0, (ncell + 1) * sizeof(int), s));
+        if (T > 0) {
+            hipLaunchKernelGGL(tri_ref_cells<true>, dim3(ref_blocks), dim3(256), 0, s, g, T, tri, h, cursor,
+                               cell_start, items, grid->n_refs);
+            hipLaunchKernelGGL(cell_sort, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, (int64_t)ncell,
+                               cell_start, items, grid->n_refs);
+        }
+        CHECK_HIP(hipGetLastError());
     }
-    CHECK_HIP(hipGetLastError());
-    size_t tb = L.scan_tmp_bytes;
-    CHECK_HIP(rocprim::exclusive_scan(w + L.scan_tmp, tb, cursor, cell_start, 0, (size_t)(ncell + 1),
-                                      rocprim::plus<int>(), s));
-    CHECK_HIP(hipMemsetAsync(cursor, 0, (ncell + 1) * sizeof(int), s));
-    if (T > 0) {
-        hipLaunchKernelGGL(tri_ref_cells<true>, dim3(ref_blocks), dim3(256), 0, s, g, T, tri, h, cursor, cell_start,
-                           items, grid->n_refs);
-        hipLaunchKernelGGL(cell_sort, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, (int64_t)ncell,
-                           cell_start, items, grid->n_refs);
-    }
-    CHECK_HIP(hipGetLastError());
+    // recount: a particle outside the grid's cells may have pairs the cell
+    // lists do not hold
+    int *outside = build_cells ? nullptr : (int *)(w + L.flag);
+    if (outside) CHECK_HIP(hipMemsetAsync(outside, 0, sizeof(int), s));
     CHECK_HIP(hipMemsetAsync(offsets, 0, sizeof(int64_t), s));
     if (N > 0) {
         hipLaunchKernelGGL(pair_count, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, g, N, px, py,
                            (const double4 *)tri4, (const float4 *)(w + L.tri32), h * h, lo2, hi2, cell_start, items,
                            grid->n_refs, offsets + 1,
-                           (uint64_t *)(w + L.mask));
+                           (uint64_t *)(w + L.mask), outside);
         CHECK_HIP(hipGetLastError());
-        tb = L.scan_tmp_bytes;
+        size_t tb = L.scan_tmp_bytes;
         CHECK_HIP(rocprim::inclusive_scan(w + L.scan_tmp, tb, offsets + 1, offsets + 1, (size_t)N,
                                           rocprim::plus<int64_t>(), s));
     }
+    int out_h = 0;
     CHECK_HIP(hipMemcpyAsync(n_pairs, offsets + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (outside) CHECK_HIP(hipMemcpyAsync(&out_h, outside, sizeof(int), hipMemcpyDeviceToHost, s));
     CHECK_HIP(hipStreamSynchronize(s));
+    if (out_h) {
+        set_error("particles outside the planned grid (or not finite): plan again");
+        return SPHBI_EGRID;
+    }
     return SPHBI_OK;
+}
+
+}  // namespace sphbi
+
+extern "C" {
+
+int sphbi_pairlist_count(int64_t N, const double *px, const double *py, int64_t T, const double *tri, double h,
+                         const sphbi_grid *grid, void *ws, size_t ws_bytes, int64_t *offsets, int64_t *n_pairs,
+                         void *stream) {
+    return pairlist_count_impl(N, px, py, T, tri, h, grid, ws, ws_bytes, offsets, n_pairs, stream, true);
+}
+
+int sphbi_pairlist_recount(int64_t N, const double *px, const double *py, int64_t T, const double *tri, double h,
+                           const sphbi_grid *grid, void *ws, size_t ws_bytes, int64_t *offsets, int64_t *n_pairs,
+                           void *stream) {
+    return pairlist_count_impl(N, px, py, T, tri, h, grid, ws, ws_bytes, offsets, n_pairs, stream, false);
 }
 
 int sphbi_pairlist_fill(int64_t N, const double *px, const double *py, int64_t T, const double *tri, double h,

@@ -34,7 +34,7 @@ import math
 
 import torch
 
-from . import integrate, kernel_preset, pairlist, pressure_contact
+from . import PairList, integrate, kernel_preset, pressure_contact
 
 
 class LibraryBoundary:
@@ -45,12 +45,13 @@ class LibraryBoundary:
         self.kernel, self.h, self.rho0 = kernel, float(h), float(rho0)
         self.tri = tri.to(torch.float64)
         self.ones = torch.ones((1, self.tri.shape[1]), dtype=torch.float64, device=self.tri.device)
+        self.pairs = PairList(self.tri, self.h)
         self.off = self.idx = None
         self.px = self.py = None
 
     def update(self, px, py):
         self.px, self.py = px, py
-        self.off, self.idx = pairlist(px, py, self.tri, self.h)
+        self.off, self.idx = self.pairs(px, py)
         return integrate(self.kernel, self.h, px, py, self.tri, self.ones, self.off, self.idx)
 
     def pressure_accel(self, p, rho):

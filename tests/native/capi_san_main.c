@@ -54,6 +54,13 @@ int main(void) {
     EXPECT(sphbi_integrate_backward(&k, &o, -1.0, 1, 0, NULL, NULL, 0, NULL, NULL, NULL, NULL, 0, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, 0, NULL) == SPHBI_EINVAL);
     EXPECT(sphbi_pressure_contact(&k, &o, 1.0, 0.0, 0, NULL, NULL, NULL, NULL, 0, NULL, NULL, NULL, 0, NULL, NULL, NULL, NULL, 0, NULL) == SPHBI_EINVAL);
     EXPECT(sphbi_mlp_workspace(-1) == 0);
+    /* pair lists: sizes, h, an unplanned grid */
+    sphbi_grid g;
+    memset(&g, 0, sizeof(g));
+    int64_t np_ = 0;
+    EXPECT(sphbi_pairlist_count(-1, p, p, 0, NULL, 1.0, &g, p, 4096, (int64_t *)p, &np_, NULL) == SPHBI_EINVAL);
+    EXPECT(sphbi_pairlist_recount(1, p, p, 0, NULL, 0.0, &g, p, 4096, (int64_t *)p, &np_, NULL) == SPHBI_EINVAL);
+    EXPECT(sphbi_pairlist_recount(1, p, p, 0, NULL, 1.0, &g, p, 4096, (int64_t *)p, &np_, NULL) == SPHBI_EINVAL);
     printf("ok\n");
     return 0;
 }

@@ -148,10 +148,60 @@ def test_pairlist_edge_cases():
     tpx, tpy, ttri = to_dev(np.array([0.1]), np.array([0.2]), np.zeros((6, 0)))
     off, idx = sb.pairlist(tpx, tpy, ttri, 0.3)
     assert off.cpu().numpy().tolist() == [0, 0]
-    # an infinite coordinate makes the bounding box non-finite: rejected by the plan
-    tpx, tpy, ttri = to_dev(np.array([0.1, np.inf]), np.array([0.2, 0.3]), tri)
+    # an infinite or NaN coordinate makes the bounding box non-finite: rejected by the plan
+    for bad in ((np.inf, 0.3), (0.4, np.nan), (np.nan, np.nan)):
+        tpx, tpy, ttri = to_dev(np.array([0.1, bad[0]]), np.array([0.2, bad[1]]), tri)
+        with pytest.raises(sb.SphbiError, match="non-finite"):
+            sb.pairlist(tpx, tpy, ttri, 0.3)
+
+
+def test_pairlist_reuse():
+    """PairList over moving particles and a fixed mesh: every list identical to
+    a fresh build, the grid reused while the particles stay inside it and
+    planned again when one leaves, fewer particles on the same grid, and the
+    C-ABI's status for a particle outside the grid or not finite."""
+    say("pairlist reuse")
+    wl = W.covering_workload(n_side=96, nx=12, ny=24, seed=2)
+    rng = np.random.default_rng(13)
+    ttri = to_dev(wl.tri)[0]
+    pl = sb.PairList(ttri, wl.h)
+    px, py = wl.px.copy(), wl.py.copy()
+    for step in range(6):
+        if step == 4:
+            px[17] = px.max() + 10.0 * wl.h                 # leaves the padded grid
+        tpx, tpy = to_dev(px, py)
+        off, idx = pl(tpx, tpy)
+        roff, ridx = sb.pairlist(tpx, tpy, ttri, wl.h)
+        assert torch.equal(off, roff) and torch.equal(idx, ridx), step
+        if step in (0, 5):
+            eoff, eidx = oracle.pairlist(px, py, wl.tri, wl.h, nthreads=NTH)
+            assert pairsets(off.cpu().numpy(), idx.cpu().numpy()) == pairsets(eoff, eidx)
+        px += rng.normal(0.0, 0.2 * wl.h, px.shape)
+        py += rng.normal(0.0, 0.2 * wl.h, py.shape)
+    say(f"  plans={pl.plans} reuses={pl.reuses}")
+    assert pl.plans == 2 and pl.reuses == 4
+    # fewer particles on the same grid
+    tpx, tpy = to_dev(px[::3], py[::3])
+    off, idx = pl(tpx, tpy)
+    roff, ridx = sb.pairlist(tpx, tpy, ttri, wl.h)
+    assert torch.equal(off, roff) and torch.equal(idx, ridx) and pl.reuses == 5
+    # through the C-ABI: outside the grid, then not finite -> SPHBI_EGRID
+    L = sb.lib()
+    s = sb._stream()
+    n = sb.C.c_int64(0)
+    for bad in (pl.grid.x0 + (pl.grid.nx + 1) * pl.grid.cell, float("nan")):
+        qx = px.copy()
+        qx[5] = bad
+        tqx, tqy = to_dev(qx, py)
+        offsets = torch.empty(len(qx) + 1, dtype=torch.int64, device=DEV)
+        rc = L.sphbi_pairlist_recount(len(qx), sb._ptr(tqx), sb._ptr(tqy), wl.n_triangles, sb._ptr(ttri), wl.h,
+                                      sb.C.byref(pl.grid), sb._ptr(pl.ws), pl.ws.numel(), sb._ptr(offsets),
+                                      sb.C.byref(n), s)
+        assert rc == sb.EGRID and b"outside" in L.sphbi_last_error()
+    # a non-finite particle through the class: the new plan rejects it
+    tqx, tqy = to_dev(qx, py)
     with pytest.raises(sb.SphbiError, match="non-finite"):
-        sb.pairlist(tpx, tpy, ttri, 0.3)
+        pl(tqx, tqy)
 
 
 # ------------------------------------------------------------------ forward
