@@ -913,11 +913,14 @@ int integrate_run(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, 
     double *rec_dd = rec_bytes >= records_bytes(T) + 256 + dd_records_bytes(T)
                          ? (double *)((char *)rec + records_bytes(T) + 256)
                          : nullptr;
+    // the refinement counter and the refinement pass's window counter sit
+    // behind the records (storage that holds them: T = 0 may come without)
+    unsigned long long *count = rec && rec_bytes >= records_bytes(T) + 256
+                                    ? (unsigned long long *)((char *)rec + records_bytes(T))
+                                    : nullptr;
     if (o.refine == SPHBI_REFINE_ALL)
         return launch_refine(order, deg, K, refine_off(), true, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, I,
-                             Gx, Gy, per_pair, s, o.pair_status, rec_dd);
-    // the refinement counter sits behind the records
-    unsigned long long *count = (unsigned long long *)((char *)rec + records_bytes(T));
+                             Gx, Gy, per_pair, s, o.pair_status, rec_dd, count ? count + 1 : nullptr);
     RefineGate gate = T > 0 ? make_gate(o, order, K) : refine_off();
     gate.count = count;
     int rc = field_prepare(h, n_nodes, T, tri, nodal, rec, rec_bytes, stream, gate.order ? count : nullptr);
@@ -926,7 +929,7 @@ int integrate_run(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, 
                         I, Gx, Gy, per_pair, s, o.pair_status);
     if (rc || !gate.order) return rc;
     return launch_refine(order, deg, K, gate, false, h, N, px, py, offsets, tri_idx, n_pairs, T, tri, nodal, I, Gx, Gy,
-                         per_pair, s, o.pair_status, rec_dd);
+                         per_pair, s, o.pair_status, rec_dd, count + 1);
 }
 
 int check_integrate_args(const sphbi_kernel *kernel, const sphbi_opts *opts, double h, int32_t n_nodes, int64_t N,

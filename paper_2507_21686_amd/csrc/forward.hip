@@ -14,7 +14,10 @@ __global__ __launch_bounds__(256) void prepare_kernel(int64_t T, const double *_
                                                       double *__restrict__ rec,
                                                       unsigned long long *__restrict__ count) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0 && count) *count = 0;      // the refinement counter of the next forward pass
+    if (t == 0 && count) {                // the refinement counter of the next forward pass
+        count[0] = 0;
+        count[1] = 0;                     // and the refinement pass's window counter
+    }
     if (t >= T) return;
     constexpr int NN = ORDER == 0 ? 1 : (ORDER == 1 ? 3 : 10);
     double v[6], A[10];

@@ -157,6 +157,7 @@ __global__ __launch_bounds__(64, fwd_waves(DEG, ORDER, MIXED)) void forward_kern
     const int64_t my_end = pid < N ? min(max(off[pid + 1], my_off), q_end) : q_end;
     const int64_t q_begin = __shfl(my_off, 0);
     double accI = 0.0, accX = 0.0, accY = 0.0;
+    unsigned long long n_skip = 0;                     // pairs left to the refinement pass (wave-uniform)
     for (int64_t base = q_begin; base < q_end; base += 64) {
         const int64_t q = base + lane;
         const int64_t qq = q < q_end ? q : q_end - 1;
@@ -183,10 +184,7 @@ __global__ __launch_bounds__(64, fwd_waves(DEG, ORDER, MIXED)) void forward_kern
                 }
                 skip = gate.fires(gx, gy);
             }
-            if (FM == kFieldPlain && ORDER >= 1 && gate.order) {
-                const unsigned long long nskip = __popcll(__ballot(skip));
-                if (lane == 0 && nskip) atomicAdd(gate.count, nskip);
-            }
+            if (FM == kFieldPlain && ORDER >= 1 && gate.order) n_skip += __popcll(__ballot(skip));
             if (t >= 0 && t < T && !skip) {   // out-of-range triangle indices contribute nothing
                 const double *r = rec + (int64_t)t * kRecDoubles;
                 constexpr int EU = fwd_edge_unroll(DEG, ORDER);
@@ -235,6 +233,10 @@ __global__ __launch_bounds__(64, fwd_waves(DEG, ORDER, MIXED)) void forward_kern
         Gx[pid] = accX;
         Gy[pid] = accY;
     }
+    // one addition per wave: an atomic per 64 pairs on the single counter
+    // held the waves up behind it (68% longer on Wendland C4 with cubic
+    // fields, where about one pair in twenty is refined)
+    if (FM == kFieldPlain && ORDER >= 1 && lane == 0 && n_skip) atomicAdd(gate.count, n_skip);
 }
 
 // Sorted variant.  The lanes of a wavefront evaluate different pairs, and an
@@ -275,6 +277,7 @@ __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_wav
     const double Rout = K.R[K.npieces - 1], R2 = Rout * Rout;
     constexpr int EU = fwd_edge_unroll(DEG, ORDER);
     double accI = 0.0, accX = 0.0, accY = 0.0;
+    unsigned long long n_skip = 0;                     // pairs left to the refinement pass (wave-uniform)
     for (int64_t sbase = q_begin; sbase < q_end; sbase += SW) {
         const int n = (int)min((int64_t)SW, q_end - sbase);
         // ---- classify: owner lane, number of near edges, rotation
@@ -309,10 +312,7 @@ __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_wav
                         rot = 16;
                     }
                 }
-                if (FM == kFieldPlain && ORDER >= 1 && gate.order) {
-                    const unsigned long long nskip = __popcll(__ballot(rot == 16));
-                    if (lane == 0 && nskip) atomicAdd(gate.count, nskip);
-                }
+                if (FM == kFieldPlain && ORDER >= 1 && gate.order) n_skip += __popcll(__ballot(rot == 16));
                 s_own[i] = (uint8_t)lo;
                 s_key[i] = (uint8_t)(near << 2 | rot);
                 cnt += (uint64_t)1 << (16 * near);
@@ -418,6 +418,10 @@ __global__ __launch_bounds__(64, FM == kFieldDivCurl ? dc_waves(ORDER) : fwd_wav
         Gx[pid] = accX;
         Gy[pid] = accY;
     }
+    // one addition per wave: an atomic per 64 pairs on the single counter
+    // held the waves up behind it (68% longer on Wendland C4 with cubic
+    // fields, where about one pair in twenty is refined)
+    if (FM == kFieldPlain && ORDER >= 1 && lane == 0 && n_skip) atomicAdd(gate.count, n_skip);
 }
 
 // Sorted or plain kernel per instantiation (measured on the covering

@@ -61,9 +61,14 @@ KArgsDD make_kargs_dd(const KArgs &K);
 // gate fires to the outputs of a forward pass run with the same gate.
 // rec_dd (dd_records_bytes(T) bytes, or null): storage for the triangles'
 // double-double records, built once per call instead of once per pair.
+// cursor (one counter, or null): the work counter through which the waves
+// share out the particle windows; the all-pairs mode clears it itself, the
+// gated mode takes it cleared by the forward pass's field preparation (the
+// word after gate.count).  Without one each wave takes a fixed share.
 int launch_refine(int order, int deg, const KArgs &K, const RefineGate &gate, bool all, double h, int64_t N,
                   const double *px, const double *py, const int64_t *off, const int32_t *tri_idx, int64_t P,
                   int64_t T, const double *tri, const double *nodal, double *I, double *Gx, double *Gy,
-                  double *per_pair, hipStream_t s, uint8_t *status = nullptr, double *rec_dd = nullptr);
+                  double *per_pair, hipStream_t s, uint8_t *status = nullptr, double *rec_dd = nullptr,
+                  unsigned long long *cursor = nullptr);
 
 }  // namespace sphbi
