@@ -648,3 +648,58 @@ def test_zero_pattern_instantiations_linear_in_kernel(order):
         err = float((lhs - rhs).abs().max() / lhs.abs().max())
         say(f"  adjoint output {comp}: relative max deviation {err:.2e}")
         assert err < 5e-11                       # measured 6e-12 (P3); a wrong instantiation errs by O(1)
+
+
+def test_refinement_bookkeeping_sparse_gate():
+    """The refinement pass's shared-out windows on the full headline workload,
+    cut to a particle count that is not a multiple of 64, with a gate that
+    selects a small share of the pairs (so that waves carry short lists over
+    many windows): every per-pair value is the FP64 pass's or the all-pairs
+    double-double pass's, bit for bit, some are the latter, and every
+    particle's sum holds each of its pairs once."""
+    wl = W.covering_workload()
+    tpx, tpy, ttri, tnod = to_dev(wl.px, wl.py, wl.tri, wl.nodal)
+    off, idx = sb.pairlist(tpx, tpy, ttri, wl.h)
+    N = wl.n_particles - 37
+    off = off[: N + 1].clone()
+    idx = idx[: int(off[-1])].clone()
+    px, py = tpx[:N].clone(), tpy[:N].clone()
+    say(f"refinement bookkeeping: N={N} P={idx.numel()}")
+    args = (wl.kernel, wl.h, px, py, ttri, tnod, off, idx)
+    plain = sb.integrate(*args, per_pair=True, refine=sb.REFINE_OFF)
+    alld = sb.integrate(*args, per_pair=True, refine=sb.REFINE_ALL)
+    auto = sb.integrate(*args, per_pair=True, refine_gate=2e5)
+    torch.cuda.synchronize()
+    pa, po, pd = auto[3], plain[3], alld[3]
+    from_dd = torch.all(pa == pd, dim=0) & ~torch.all(pa == po, dim=0)
+    assert bool(torch.all(torch.all(pa == po, dim=0) | torch.all(pa == pd, dim=0)))
+    frac = float(from_dd.double().mean())
+    say(f"  {frac:.4%} of the pairs from the double-double pass")
+    assert 0.0 < frac < 0.5
+    owner = torch.repeat_interleave(torch.arange(N, device=DEV), off[1:] - off[:-1])
+    amax = float(np.abs(wl.nodal).max()) * 3.0
+    for k in range(3):
+        s = torch.zeros(N, dtype=torch.float64, device=DEV).index_add_(0, owner, pa[k])
+        err = float((torch.abs(s - auto[k]) / amax).max())
+        assert err < (1e-12 if k == 0 else 1e-12 / wl.h), (k, err)
+
+
+def test_refinement_all_pairs_without_workspace():
+    """The all-pairs mode through the C-ABI with no triangles and no workspace
+    (each wave then takes a fixed share of the windows): every output written,
+    as zeros."""
+    say("refinement all pairs, T = 0, no workspace")
+    N = 200
+    px = torch.zeros(N, dtype=torch.float64, device=DEV)
+    off = torch.zeros(N + 1, dtype=torch.int64, device=DEV)
+    out = [torch.full((N,), float("nan"), dtype=torch.float64, device=DEV) for _ in range(3)]
+    k = sb.kernel_preset(0)
+    o = sb.opts(refine=sb.REFINE_ALL)
+    n = sb.C.c_void_p(None)
+    rc = sb.lib().sphbi_integrate(sb.C.byref(k), sb.C.byref(o), 0.1, 1, N, sb._ptr(px), sb._ptr(px), 0, n, n,
+                                  sb._ptr(off), n, 0, sb._ptr(out[0]), sb._ptr(out[1]), sb._ptr(out[2]), n, n, 0,
+                                  sb._stream())
+    torch.cuda.synchronize()
+    assert rc == 0, sb.lib().sphbi_last_error()
+    for t in out:
+        assert bool(torch.all(t == 0.0))
