@@ -184,8 +184,8 @@ int sphbi_pairlist_fill(int64_t N, const double *px, const double *py, int64_t T
  *
  * sphbi_integrate_workspace: bytes of device workspace sphbi_integrate needs
  * for T triangles: per-triangle field records (128 B each), the refinement
- * counter, and the refinement pass's double-double records (256 B each).
- * Host only.
+ * pass's counters (256 B: pairs left out, windows handed out), and its
+ * double-double records (256 B each).  Host only.
  *
  * sphbi_integrate: I, Gx, Gy [N] per particle = sum over its pairs; if
  * per_pair is not NULL also the per-pair values [3][P].  Positions and h in
