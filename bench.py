@@ -236,6 +236,52 @@ def bench_refinement_cost(args, sb, W, torch, dev):
     return out
 
 
+def device_peaks(sb, torch, dev):
+    """The peaks checked on the device itself: the compute units and maximum
+    clock that rocminfo reports and the FP64 vector peak they imply (128 FP64
+    operations per compute unit and clock), the rate of the library's FP64 FMA
+    probe, and the rate of a 1 GiB device-to-device copy (bytes read plus
+    bytes written).  roofline.peak stays the published figure."""
+    import re
+    import subprocess
+    out = {"rocminfo": None}
+    try:
+        txt = subprocess.run(["rocminfo"], capture_output=True, text=True, timeout=60).stdout
+        for sec in re.split(r"\n\s*Agent \d+\s*\n", txt):
+            name = re.search(r"Name:\s+(gfx\w+)", sec)
+            cu = re.search(r"Compute Unit:\s+(\d+)", sec)
+            mhz = re.search(r"Max Clock Freq\. \(MHz\):\s+(\d+)", sec)
+            if name and cu and mhz:
+                n_cu, f = int(cu.group(1)), int(mhz.group(1))
+                out["rocminfo"] = {"name": name.group(1), "compute_units": n_cu, "max_clock_mhz": f}
+                out["fp64_vector_peak_from_rocminfo_tflops"] = n_cu * 128 * f * 1e6 / 1e12
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        sb.probe_fp64_fma(16384, sink)
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    flops = sum(sb.probe_fp64_fma(16384, sink) for _ in range(10))
+    b.record(stream)
+    torch.cuda.synchronize()
+    out["fp64_fma_probe_tflops"] = flops / (a.elapsed_time(b) * 1e-3) / 1e12
+    x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    a.record(stream)
+    for _ in range(10):
+        y.copy_(x)
+    b.record(stream)
+    torch.cuda.synchronize()
+    out["copy_1gib_gbps"] = 10 * 2 * x.numel() * 8 / (a.elapsed_time(b) * 1e-3) / 1e9
+    out["published"] = {"fp64_vector_tflops": FP64_VECTOR_PEAK_TFLOPS, "hbm_gbps": 8000.0}
+    return out
+
+
 def kernel_c_d_int_k(sb, kid):
     """c_d * int_0^1 k(q) dq of a preset: the gradient of a half plane through the particle is twice this / h"""
     k = sb.kernel_preset(kid)
@@ -732,6 +778,11 @@ def main():
         result["modes"]["adjoint"] = bench_adjoint(args, sb, W, torch, dev)
     if not args.no_surrogate:
         result["modes"]["surrogate"] = bench_surrogate(args, sb, torch, dev)
+
+    result["peaks"] = device_peaks(sb, torch, dev)
+    pk = result["peaks"]
+    log(f"bench: peaks: rocminfo {pk['rocminfo']}, FP64 FMA probe {pk['fp64_fma_probe_tflops']:.1f} TFLOP/s, "
+        f"1 GiB copy {pk['copy_1gib_gbps']:.0f} GB/s")
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args, wl, off_h, idx_h)

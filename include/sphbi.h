@@ -427,6 +427,18 @@ int sphbi_surrogate_integrate(const sphbi_kernel *kernel /* host */, double h, i
                               float threshold, double *I, double *Gx, double *Gy, double *per_pair, uint8_t *flags,
                               int64_t *n_flagged, void *ws, size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Measurement probe (not part of the method): the device's FP64 vector FMA
+ * rate, against which the pair kernels' FP64 rates are compared.  Launches
+ * eight waves per SIMD, each lane running 8 independent chains of `iters`
+ * dependent fused multiply-adds (1 <= iters <= 2^24, else SPHBI_EINVAL).
+ * *flops (host) receives the FP64 operations the launch executes (an FMA
+ * counts two); time the launch on `stream` to get the rate.  sink: one
+ * device double, never written in practice (it keeps the chains live).
+ * Asynchronous.
+ * ------------------------------------------------------------------- */
+int sphbi_probe_fp64_fma(int64_t iters, double *sink, double *flops /* host out */, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

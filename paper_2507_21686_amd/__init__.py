@@ -29,7 +29,7 @@ EXPORTS = ["sphbi_kernel_preset", "sphbi_default_opts", "sphbi_last_error", "sph
            "sphbi_integrate_backward", "sphbi_surrogate_features", "sphbi_surrogate_targets", "sphbi_mlp_workspace", "sphbi_mlp_forward",
            "sphbi_mlp_loss_grad", "sphbi_adam_step", "sphbi_surrogate_model_bytes", "sphbi_surrogate_pack",
            "sphbi_surrogate_workspace", "sphbi_surrogate_integrate", "sphbi_operator_workspace", "sphbi_operator",
-           "sphbi_pressure_contact", "sphbi_integrate_quadrature", "sphbi_integrate_noalloc"]
+           "sphbi_pressure_contact", "sphbi_integrate_quadrature", "sphbi_integrate_noalloc", "sphbi_probe_fp64_fma"]
 MLP_PARAMS = 34692
 NOALLOC_MAX_TRIANGLES = 131072
 
@@ -111,6 +111,7 @@ def lib():
         L.sphbi_surrogate_workspace.restype = C.c_size_t
         L.sphbi_surrogate_integrate.argtypes = [C.POINTER(SphbiKernel), d, i64, vp, vp, i64, vp, vp, vp, vp, i64,
                                                 vp, f, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.sphbi_probe_fp64_fma.argtypes = [i64, vp, C.POINTER(C.c_double), vp]
         _lib = L
     return _lib
 
@@ -489,6 +490,16 @@ def pressure_contact(kernel, h, rho0, px, py, p_particle, rho_particle, tri, off
 # quadrature of the same sums (the comparison of Sec. 6.1-6.2)
 # ----------------------------------------------------------------------------
 MAX_GAUSS = 64
+
+
+def probe_fp64_fma(iters: int, sink):
+    """``sphbi_probe_fp64_fma``: launches the FP64 FMA probe on the current
+    stream and returns the FP64 operations it executes (time it to get the
+    device's FP64 vector rate).  sink: a one-element float64 device tensor."""
+    sink = _dev(sink)
+    flops = C.c_double(0.0)
+    _check(lib().sphbi_probe_fp64_fma(int(iters), _ptr(sink), C.byref(flops), _stream()), "sphbi_probe_fp64_fma")
+    return flops.value
 
 
 def integrate_quadrature(kernel, h, px, py, tri, nodal, offsets, tri_idx, n_gauss):

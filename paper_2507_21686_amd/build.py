@@ -12,7 +12,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsphbi.so")
-SOURCES = ["capi.hip", "forward.hip", "adjoint.hip", "adjoint_linear.hip", "operators.hip", "quadrature.hip", "mlp.hip", "serve.hip", "noalloc.hip", "refine.hip"]
+SOURCES = ["capi.hip", "forward.hip", "adjoint.hip", "adjoint_linear.hip", "operators.hip", "quadrature.hip", "mlp.hip", "serve.hip", "noalloc.hip", "refine.hip", "probe.hip"]
 ARCH = os.environ.get("SPHBI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -61,6 +61,10 @@ int main(void) {
     EXPECT(sphbi_pairlist_count(-1, p, p, 0, NULL, 1.0, &g, p, 4096, (int64_t *)p, &np_, NULL) == SPHBI_EINVAL);
     EXPECT(sphbi_pairlist_recount(1, p, p, 0, NULL, 0.0, &g, p, 4096, (int64_t *)p, &np_, NULL) == SPHBI_EINVAL);
     EXPECT(sphbi_pairlist_recount(1, p, p, 0, NULL, 1.0, &g, p, 4096, (int64_t *)p, &np_, NULL) == SPHBI_EINVAL);
+    /* the FP64 probe: iteration count and outputs */
+    double fl = 0.0;
+    EXPECT(sphbi_probe_fp64_fma(0, p, &fl, NULL) == SPHBI_EINVAL);
+    EXPECT(sphbi_probe_fp64_fma(16, p, NULL, NULL) == SPHBI_EINVAL);
     printf("ok\n");
     return 0;
 }

@@ -46,7 +46,7 @@ def test_library_host_code_under_asan_ubsan():
     from concurrent.futures import ThreadPoolExecutor
     tmp = tempfile.mkdtemp(prefix="san_capi_")
     names = ("capi", "forward", "adjoint", "adjoint_linear", "operators", "quadrature", "mlp", "serve", "noalloc",
-             "refine")
+             "refine", "probe")
 
     def compile_one(name):
         obj = os.path.join(tmp, name + ".o")
