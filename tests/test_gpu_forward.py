@@ -204,6 +204,32 @@ def test_pairlist_reuse():
         pl(tqx, tqy)
 
 
+def test_pairlist_reuse_edge_cases():
+    """PairList with no particles, with an empty mesh, and a call with more
+    particles than the kept workspace holds (planned again)."""
+    say("pairlist reuse edge cases")
+    tri = W.box_mesh_8()
+    ttri = to_dev(tri)[0]
+    pl = sb.PairList(ttri, 0.3)
+    e = torch.zeros(0, dtype=torch.float64, device=DEV)
+    off, idx = pl(e, e)
+    assert off.cpu().tolist() == [0] and idx.numel() == 0
+    off, idx = pl(e, e)                                    # the empty grid kept
+    assert pl.plans == 1 and pl.reuses == 1
+    rng = np.random.default_rng(14)
+    px, py = rng.uniform(-0.5, 1.5, 300), rng.uniform(-0.5, 1.5, 300)
+    tpx, tpy = to_dev(px, py)
+    off, idx = pl(tpx, tpy)                                # more particles: planned again
+    roff, ridx = sb.pairlist(tpx, tpy, ttri, 0.3)
+    assert pl.plans == 2 and torch.equal(off, roff) and torch.equal(idx, ridx)
+    # an empty mesh: no pairs, the grid kept
+    pe = sb.PairList(torch.zeros((6, 0), dtype=torch.float64, device=DEV), 0.3)
+    for _ in range(2):
+        off, idx = pe(tpx, tpy)
+        assert int(off[-1]) == 0 and idx.numel() == 0
+    assert pe.plans == 1 and pe.reuses == 1
+
+
 # ------------------------------------------------------------------ forward
 
 def check_forward(wl, tol_i=1e-12, tol_g=1e-12, sample=None, refine=sb.REFINE_AUTO):
