@@ -81,30 +81,28 @@ __device__ __noinline__ void pair_dd(const KArgsDD &K, double x, double y, doubl
     oY = (double)Y;
 }
 
-// The pairs to refine (every pair with a valid triangle in the all-pairs
-// mode, else those whose gate fires) are spread unevenly over the particles:
-// on a covering mesh with Wendland C4 and cubic fields the 256-particle
-// windows hold 0 to 150 of them.  Each wavefront therefore takes windows of
-// 64 particles (the first by its index, then from a counter `cursor`,
-// zeroed before the launch; without one, every gridDim.x-th window from its
-// own index) until none is left, sweeps each window's pairs 64 at a time,
-// one pair per lane, and appends the pairs to refine to a list in LDS, in
-// pair order.  The list carries
-// over from window to window: whenever it holds kRefBatch entries, the first
-// kRefBatch are evaluated one pair per lane, so that the costly
-// double-double rounds run full, and a wave ends with one partial batch.
-// The results are added to per-particle sums in LDS in list order, one
-// accumulator slot per window (kRefSlots of them); a window's sums are
-// written out once it has been swept and its last listed pair evaluated.
-// When every slot is taken, a batch of what is listed frees them.  As in the
-// sorted FP64 kernel, the pairs of a batch are evaluated in the order of
-// their near-edge counts, most first, each triangle's edge loop starting at
-// its near edges, so that the lanes of a round take the same branches
-// (batches of two rounds measured up to 10% slower on the covering meshes).
-// The sums stay in pair order, whichever wave takes a window and wherever
-// the batches split it (deterministic).  A wave's first window is the one
-// of its own index and the counter hands out the rest, so that no wave
-// waits on the counter before it starts.
+// The pairs to refine (every pair with a valid triangle in the all-pairs mode,
+// else those whose gate fires) are spread unevenly over the particles: on a
+// covering mesh with Wendland C4 and cubic fields the 256-particle windows hold
+// 0 to 150 of them.  Each wavefront therefore takes windows of 64 particles
+// (the first by its index, then from a counter `cursor`, zeroed before the
+// launch; without one, every gridDim.x-th window from its own index) until none
+// is left, sweeps each window's pairs 64 at a time, one pair per lane, and
+// appends the pairs to refine to a list in LDS, in pair order.  The list
+// carries over from window to window: whenever it holds kRefBatch entries, the
+// first kRefBatch are evaluated one pair per lane, so that the costly
+// double-double rounds run full, and a wave ends with one partial batch. The
+// results are added to per-particle sums in LDS in list order, one accumulator
+// slot per window (kRefSlots of them); a window's sums are written out once it
+// has been swept and its last listed pair evaluated. When every slot is taken,
+// a batch of what is listed frees them.  As in the sorted FP64 kernel, the
+// pairs of a batch are evaluated in the order of their near-edge counts, most
+// first, each triangle's edge loop starting at its near edges, so that the
+// lanes of a round take the same branches (batches of two rounds measured up to
+// 10% slower on the covering meshes). The sums stay in pair order, whichever
+// wave takes a window and wherever the batches split it (deterministic).  A
+// wave's first window is the one of its own index and the counter hands out the
+// rest, so that no wave waits on the counter before it starts.
 constexpr int kRefBatch = 64;                 // pairs evaluated together (one round)
 constexpr int kRefList = kRefBatch + 64;      // < kRefBatch listed + one sweep step of 64
 constexpr int kRefSlots = 16;
@@ -258,18 +256,19 @@ __global__ __launch_bounds__(64) void refine_kernel(const KArgsDD K, RefineGate 
         // a free slot.  Every taken slot has pending pairs (a window is
         // retired as soon as it has none), and fewer than kRefBatch are listed
         // between windows, so one batch evaluates them all and frees every
-        // slot.  (The last lines only bound the search.)
+        // slot.  The loop ends in any case: each pass evaluates listed pairs,
+        // and with none listed no slot has pending pairs, so all can retire.
         int sl = -1;
-        for (int k = 0; k < kRefSlots && sl < 0; ++k)
-            if (s_w0[k] < 0) sl = k;
-        if (sl < 0) {
-            flush(-1);
+        for (;;) {
             for (int k = 0; k < kRefSlots && sl < 0; ++k)
                 if (s_w0[k] < 0) sl = k;
-        }
-        if (sl < 0) {
-            retire(0);
-            sl = 0;
+            if (sl >= 0) break;
+            if (n_list > 0) {
+                flush(-1);
+            } else {
+                for (int k = 0; k < kRefSlots; ++k)
+                    if (s_w0[k] >= 0) retire(k);
+            }
         }
         sync();
         if (lane == 0) {
