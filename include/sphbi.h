@@ -208,7 +208,8 @@ int sphbi_integrate(const sphbi_kernel *kernel /* host */, const sphbi_opts *opt
  * sphbi_integrate, minus ws/ws_bytes.  The per-triangle field records go to
  * a fixed array inside this library (one copy per GPU, allocated with the
  * code object and held until the process ends) of SPHBI_NOALLOC_MAX_TRIANGLES
- * records, 16 MiB; T above that returns SPHBI_EUNSUPPORTED and launches
+ * records, 48 MiB with the refinement pass's counters and double-double
+ * records; T above that returns SPHBI_EUNSUPPORTED and launches
  * nothing.  No call allocates or frees memory.  The first call on a device
  * looks up that device's array address (synchronous, once per device).
  * Every call on one GPU shares its array: calls that overlap in time on

@@ -17,9 +17,10 @@ namespace {
 constexpr int64_t kNoAllocMaxT = SPHBI_NOALLOC_MAX_TRIANGLES;
 constexpr int kMaxDevices = 64;
 
-// Field records of at most kNoAllocMaxT triangles (16 MiB) and the
-// refinement counter behind them (the layout of sphbi_integrate's workspace).
-constexpr size_t kScratchDoubles = kNoAllocMaxT * kRecDoubles + 32;
+// Field records of at most kNoAllocMaxT triangles (16 MiB), the refinement
+// pass's counters behind them and its double-double records (32 MiB): the
+// layout of sphbi_integrate's workspace.
+constexpr size_t kScratchDoubles = kNoAllocMaxT * kRecDoubles + 32 + 2 * kNoAllocMaxT * kRecDoubles;
 __device__ __align__(256) double scratch[kScratchDoubles];
 
 std::mutex g_mu;
@@ -68,8 +69,10 @@ extern "C" int sphbi_integrate_noalloc(const sphbi_kernel *kernel, const sphbi_o
     rc = scratch_ptr(&rec);
     if (rc) return rc;
     const size_t bytes = kScratchDoubles * sizeof(double);
-    static_assert(kScratchDoubles * sizeof(double) >= kNoAllocMaxT * kRecDoubles * sizeof(double) + 256,
-                  "records and counter must fit");
+    // (kNoAllocMaxT records take a multiple of 256 bytes, as records_bytes rounds to)
+    static_assert((kNoAllocMaxT * kRecDoubles * sizeof(double)) % 256 == 0 &&
+                      kScratchDoubles * sizeof(double) >= 3 * kNoAllocMaxT * kRecDoubles * sizeof(double) + 256,
+                  "records, counters and double-double records must fit");
     return integrate_run(kernel, opts, h, n_nodes, N, px, py, T, tri, nodal, rec, bytes, offsets, tri_idx, n_pairs, I,
                          Gx, Gy, per_pair, stream);
 }
