@@ -729,3 +729,21 @@ def test_refinement_all_pairs_without_workspace():
     assert rc == 0, sb.lib().sphbi_last_error()
     for t in out:
         assert bool(torch.all(t == 0.0))
+
+
+@pytest.mark.parametrize("kid", [1, 2])
+def test_refinement_deterministic_across_runs(kid):
+    """The refinement pass hands its windows out through a counter, so which
+    wave evaluates which pairs changes from run to run; the sums must not:
+    five runs of the default call (Wendland C4: a few per cent of the pairs
+    refined; C6: all of them), and of the all-pairs mode, bit for bit."""
+    wl = W.covering_workload(n_side=512, nx=64, ny=128, seed=4, kernel=kid, field_order=3)
+    say(f"refinement determinism kid={kid}")
+    t = to_dev(wl.px, wl.py, wl.tri, wl.nodal)
+    off, idx = sb.pairlist(t[0], t[1], t[2], wl.h)
+    for refine in (sb.REFINE_AUTO, sb.REFINE_ALL):
+        first = sb.integrate(kid, wl.h, *t, off, idx, per_pair=True, refine=refine)
+        for _ in range(4):
+            again = sb.integrate(kid, wl.h, *t, off, idx, per_pair=True, refine=refine)
+            for a, b in zip(first, again):
+                assert torch.equal(a, b)
