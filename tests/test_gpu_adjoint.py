@@ -118,11 +118,18 @@ def test_every_instantiation_nodal_and_leibniz(kid, order):
     err = np.abs(dnod - ref).max() / np.abs(ref).max()
     say(f"  nodal scaled error {err:.2e}")
     assert err <= 1e-13 * kfac
+    # both sides are FP64 evaluations of the same integrals (the adjoint's
+    # moments against the forward pass), so they differ by rounding that
+    # scales with the kernel's cancellation factor K_f, and for cubic fields
+    # with the extrapolation of the field about the particle: 5 eps' K_f with
+    # eps' = 1e-15, four times that for cubic fields (measured on this
+    # workload: 2e-15 ... 4.8e-12, between 4x and 44x below the bound)
     scale = float(torch.maximum(torch.abs(Gx), torch.abs(Gy)).max())
+    bound = 5e-15 * kfac * (4.0 if order == 3 else 1.0)
     for d, gg in ((dpx, Gx), (dpy, Gy)):
         e = float(torch.abs(d - gg).max()) / scale
-        say(f"  leibniz scaled error {e:.2e}")
-        assert e < 5e-10
+        say(f"  leibniz scaled error {e:.2e} (bound {bound:.1e})")
+        assert e < bound
 
 
 @pytest.mark.parametrize("kid,order", [(0, 0), (1, 3), (3, 1), (2, 3)])
