@@ -377,7 +377,7 @@ def test_forward_degenerate_geometry_fields(kid, order):
         scale = max(1.0, np.abs(ref[k]).max())
         err = np.abs(got[k] - ref[k]).max() / scale
         say(f"  component {k}: scaled error {err:.2e}")
-        assert err < 1e-11
+        assert err < 1e-12                       # the FP64 target (measured at most 1.0e-13, C6 with P3)
 
 
 @pytest.mark.parametrize("kid,order", [(1, 1), (0, 3), (0, 0), (3, 3)])
